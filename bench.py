@@ -1,0 +1,170 @@
+"""Throughput of the fused P-LBM step on one MI355X.
+
+Workload (the step the metric is quoted on): D3Q19 static droplet, 256^3
+periodic lattice, float32 populations and arithmetic (psi evaluated in
+float64), MRT collision with Guo forcing, lattice Peng-Robinson EOS at
+T/Tc = 0.8 (acentric factor 0.326), eps = 2, kappa = 1, tau = 1, droplet
+radius 48 with a tanh interface of width 5.  Synthetic input, resident in HBM
+before timing starts.
+
+A timed step is one fused update of every node (psi, force stencil, MRT
+collision with forcing, streaming); the global reduction (mass, momentum,
+max|u|, residual, health flags) runs every 100 steps inside the timed region,
+as in a production run.
+
+Prints one JSON line.  `roofline` reports the step kernel's algorithmic HBM
+traffic (2 Q S bytes per node update: read and write 19 float32 populations)
+over its average launch duration measured with HIP events on the lattice's
+stream; `cpu_baseline` times the FP64 NumPy oracle on a bounded sample of the
+same workload on the host.
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+REDUCE_EVERY = 100
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(seconds=12.0):
+    """Time the oracle on a 48^3 D3Q19 MRT droplet (same physics) in a child process, one thread."""
+    code = r"""
+import os, sys, time, json
+sys.path.insert(0, %r)
+import numpy as np
+import plbm_synth as syn
+from oracle import eos as E, params as P, step as S
+from oracle.lattice import D3Q19
+e = E.PengRobinsonEOS(0.8, 0.326)
+rv, rl, _ = P.coexistence(e, 2.0)
+dims = (48, 48, 48)
+co = syn.grid(dims)
+rho = syn.droplet(co, dims, rv, rl, R=9.0, W=5.0)
+p = S.StepParams(D3Q19, e, eps=2.0, kappa=1.0, tau_v=1.0, tau_l=1.0, rho_v=rv, rho_l=rl, collision="mrt")
+f = S.init_equilibrium(D3Q19, rho)
+f = S.step(p, f)
+t0 = time.perf_counter(); n = 0
+while time.perf_counter() - t0 < %f:
+    f = S.step(p, f); n += 1
+dt = time.perf_counter() - t0
+print(json.dumps({"mlups": rho.size * n / dt / 1e6, "steps": n, "seconds": dt, "nodes": rho.size}))
+""" % (ROOT, seconds)
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[k] = "1"
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        log(r.stderr[-2000:])
+        return None
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": round(out["mlups"], 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 NumPy oracle, D3Q19 48^3 MRT droplet (same EOS/physics), {out['steps']} steps "
+                      f"in {out['seconds']:.1f} s, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the lattice update is not sharded across GPUs here); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+
+    N.load()
+    n = args.size
+    dims = (n, n, n)
+    prm = N.plbm_params_pr_lattice(0.8, 0.326, 2.0, 1.0, 1.0, 1.0)
+    log(f"[bench] coexistence rho_v={prm.rho_v:.6f} rho_l={prm.rho_l:.6f}")
+    lat = Lattice("D3Q19", dims, prm, collision="mrt", storage="f32")
+    R = 48.0 * n / 256.0
+    lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=5.0, R=R, centre=[n / 2.0] * 3)
+    stream = lat.stream
+    log(f"[bench] lattice {dims} D3Q19 MRT f32, {lat.nbytes / 2**30:.2f} GiB; warmup {args.warmup}")
+    lat.step(args.warmup)
+    d0 = lat.reduce()
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done: mass={d0.mass:.6e} max_u={d0.max_u:.3e}")
+
+    ev = []
+    K = args.steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    n_reduce = 0
+    while done < K:
+        chunk = min(REDUCE_EVERY, K - done)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lat.step(chunk)
+        e1.record(stream)
+        ev.append((e0, e1, chunk))
+        done += chunk
+        if done % REDUCE_EVERY == 0:
+            d = lat.reduce()
+            n_reduce += 1
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    kernel_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
+    avg_kernel_s = kernel_ms / 1e3 / K
+    nodes = lat.N
+    ms_per_step = wall * 1e3 / K
+    mlups = nodes * K / wall / 1e6
+    bytes_per_launch = 2 * 19 * 4 * nodes
+    achieved = bytes_per_launch / avg_kernel_s / 1e9
+    dfin = lat.reduce()
+    log(f"[bench] {K} steps in {wall:.3f} s; step kernel avg {avg_kernel_s * 1e3:.4f} ms; "
+        f"mass drift {(dfin.mass - d0.mass) / d0.mass:.2e}; flags {dfin.flags}")
+    if dfin.flags & (N.PLBM_FLAG_NAN | N.PLBM_FLAG_RHO_NONPOS):
+        log("[bench] lattice became unstable")
+        sys.exit(3)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
+    out = {
+        "metric": "MLUPS & % HBM peak (D3Q19 P-LBM step); solves/s + p99 latency at fixed accuracy",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"D3Q19 static droplet {n}^3 periodic, f32 populations, MRT + Guo forcing, "
+                               f"Peng-Robinson T/Tc=0.8, radius {R:g}, tanh width 5; reduction every "
+                               f"{REDUCE_EVERY} steps",
+                   "lattice": "D3Q19", "nodes": nodes, "storage": "f32", "collision": "mrt",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    lat.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,273 @@
+/*
+ * plbm.h -- C ABI of libplbm, the MI355X (gfx950) implementation of the
+ * pseudo-potential lattice Boltzmann (P-LBM) update of Czelusniak, Bingert,
+ * Krause and Simonis, "On the consistency of pseudo-potential lattice
+ * Boltzmann methods" (arXiv 2504.15018).
+ *
+ * What one step computes (Sec. II of the paper, lattice units dx = dt = 1,
+ * G = -1):
+ *   rho = sum_i f_i                                   eq. (Density)
+ *   psi = sqrt(2 (rho/3 - p_EOS(rho)))                eq. (Interaction_Potential)
+ *   M1, M2 = stencil moments of psi over all directions  (Sec. II, M^(1), M^(2))
+ *   F   = -G psi M1 + (G/4) eps M1.M2 - (G/6)(kappa-1)(M1.M2 - M1 tr M2) + F_g
+ *                                                     eq. (interactionForce);
+ *         the eps coefficient is the one that reproduces the paper's pressure
+ *         tensor, eq. (New_Pressure_Tensor)
+ *   u   = (sum_i f_i c_i + F/2) / rho                 eq. (Momentum)
+ *   tau = tau_v + (rho - rho_v)/(rho_l - rho_v) (tau_l - tau_v)   (Sec. VI)
+ *   BGK collision, eq. (LBE), with Guo forcing, eq. (Guo_Forcing_Scheme), or
+ *   the MRT extension; streaming with periodic wrap or half-way bounce-back.
+ *
+ * Conventions for every call:
+ *   - Every function returns an int status: PLBM_OK (0) or a negative
+ *     PLBM_E_* code.  No C++ exception crosses this boundary.  On error,
+ *     plbm_last_error() returns a message (thread-local, owned by the library,
+ *     valid until the next call on the same thread).
+ *   - Populations and fields exchanged with the caller are float64, in
+ *     structure-of-arrays layout with x fastest: f[q][z][y][x] (3-D) or
+ *     f[q][y][x] (2-D); vector fields u[a][...] likewise, a = 0..d-1.
+ *   - D2Q9 direction order is that of eq. (VelocitySet): rest, (1,0), (0,1),
+ *     (-1,0), (0,-1), (1,1), (-1,1), (-1,-1), (1,-1).
+ *     D3Q19 order: rest; (1,0,0), (-1,0,0), (0,1,0), (0,-1,0), (0,0,1),
+ *     (0,0,-1); (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1),
+ *     (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1).
+ *   - Device memory is owned by the caller (for example a PyTorch uint8
+ *     tensor); the library never allocates device memory.  Host buffers
+ *     passed in are read or written during the call only.
+ *   - Handles are not thread-safe; use one handle per stream.
+ */
+#ifndef PLBM_H
+#define PLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PLBM_ABI_VERSION 1
+
+/* status codes */
+#define PLBM_OK 0
+#define PLBM_E_INVALID (-1)     /* argument out of range or inconsistent */
+#define PLBM_E_UNSUPPORTED (-2) /* combination not built (see plbm_create) */
+#define PLBM_E_NOMEM (-3)       /* caller's device buffer too small */
+#define PLBM_E_DEVICE (-4)      /* HIP runtime error; message carries the HIP string */
+#define PLBM_E_UNSTABLE (-5)    /* health flags raised (NaN, rho <= 0) */
+#define PLBM_E_NOCONVERGE (-6)  /* parameter root solve did not converge */
+
+/* lattice kinds */
+#define PLBM_D2Q9 0
+#define PLBM_D3Q19 1
+/* collision operators */
+#define PLBM_BGK 0
+#define PLBM_MRT 1
+/* population storage */
+#define PLBM_F64 0   /* float64 storage and arithmetic */
+#define PLBM_F32 1   /* float32 storage and arithmetic; psi(rho) evaluated in float64 */
+#define PLBM_F16S 2  /* IEEE half storing f_i - w_i rho0; float32 arithmetic; float64 psi */
+#define PLBM_BF16S 3 /* bfloat16 storing f_i - w_i rho0; float32 arithmetic; float64 psi */
+/* boundary kinds, per axis */
+#define PLBM_PERIODIC 0
+#define PLBM_HALFWAY_BB 1 /* walls half a spacing outside the first and last node */
+/* equations of state */
+#define PLBM_EOS_PAPER 0        /* eq. (EOS) of Sec. IV */
+#define PLBM_EOS_PENG_ROBINSON 1 /* Peng-Robinson, lattice constants a = 2/49, b = 2/21, R = 1 */
+/* health flags of plbm_diag.flags */
+#define PLBM_FLAG_NAN 1
+#define PLBM_FLAG_RHO_NONPOS 2
+#define PLBM_FLAG_PSI_NEG 4 /* psi radicand < 0 somewhere (clamped to 0) */
+
+/* Physical (SI) description of the fluid and problem (Sec. V, Table I). */
+typedef struct plbm_phys_params {
+  int32_t eos;           /* PLBM_EOS_* */
+  int32_t pad0;
+  double rho_v, rho_l;   /* kg/m^3: coexistence densities (paper EOS: imposed) */
+  double nu_v, nu_l;     /* m^2/s: kinematic viscosities of vapour and liquid */
+  double gamma;          /* N/m: surface tension; <= 0 selects kappa = 1 */
+  double xi;             /* m: interface width (paper EOS, eq. thickness) */
+  double L;              /* m: characteristic length L_phs of eq. (unit) */
+  double body_force[3];  /* N/m^3 */
+  double T_over_Tc;      /* Peng-Robinson: reduced temperature */
+  double omega;          /* Peng-Robinson: acentric factor */
+  double epsilon;        /* mechanical-stability parameter; 0 selects 2 (Sec. IV) */
+  double U_phys;         /* m/s: optional characteristic velocity for Re (0: none) */
+} plbm_phys_params;
+
+/* The converter's three lattice inputs, eq. (unit): L_lat, nu_l,lat (through
+ * tau_l, nu = (tau - 1/2)/3), rho_l,lat. */
+typedef struct plbm_lattice_map {
+  double L_lat;
+  double tau_l;
+  double rho_l_lat; /* 0 selects 1.187 (Sec. VI) */
+} plbm_lattice_map;
+
+/* Resolved constants in lattice units, as consumed by plbm_create. */
+typedef struct plbm_lattice_params {
+  int32_t eos;
+  int32_t pad0;
+  double K;                    /* paper EOS: p_c / rho_c^3 from eq. (thickness) */
+  double eos_rho_v, eos_rho_l; /* paper EOS: the densities inside eq. (EOS) */
+  double pr_a, pr_b, pr_R, pr_T, pr_alpha; /* Peng-Robinson constants */
+  double rho_v, rho_l;         /* coexistence densities predicted by the
+                                  mechanical-stability condition (Sec. IV);
+                                  they anchor tau(rho) */
+  double epsilon, kappa, G;    /* eq. (interactionForce); G = -1 */
+  double tau_v, tau_l;         /* relaxation times of vapour and liquid */
+  double body_force[3];        /* lattice units */
+  double C_L, C_T, C_M, C_U, C_VF, C_gamma, C_p; /* eqs. (unit), (unit2); 0 if none */
+  double Re;                   /* U_phys L / nu_l when U_phys > 0, else 0 */
+  double gamma_lat;            /* lattice surface tension (0 if kappa set directly) */
+} plbm_lattice_params;
+
+/* Geometry, operator and storage of one lattice. */
+typedef struct plbm_lattice_desc {
+  int32_t lattice;   /* PLBM_D2Q9 | PLBM_D3Q19 */
+  int32_t collision; /* PLBM_BGK | PLBM_MRT */
+  int32_t storage;   /* PLBM_F64 | PLBM_F32 | PLBM_F16S | PLBM_BF16S */
+  int32_t nx, ny, nz; /* nodes per axis; D2Q9 uses nx, ny and requires nz = 1 */
+  int32_t bc[3];      /* per axis x, y, z: PLBM_PERIODIC or PLBM_HALFWAY_BB.
+                         Walls are supported on the last axis only (z in 3-D,
+                         y in 2-D); other axes must be periodic. */
+  int32_t pad0;
+  double rho0_shift;  /* reference density of shifted storage (F16S/BF16S);
+                         0 selects rho_l of the parameters */
+  double mrt_rates[4]; /* MRT rates s_e, s_eps, s_q, s_m; 0 selects 0.8, 0.8,
+                          1.1, 1.1.  Stress (and D3Q19 pi) moments relax at
+                          1/tau(rho); momentum moments are rate-independent. */
+} plbm_lattice_desc;
+
+/* Initial density shape evaluated on the device (tanh interfaces of width W,
+ * nodes at integer positions). */
+#define PLBM_SHAPE_SLAB 0    /* liquid in the central half of axis `axis` */
+#define PLBM_SHAPE_DROPLET 1 /* liquid sphere/disc of radius R at centre[] */
+#define PLBM_SHAPE_LAYERS 2  /* liquid below `level` along axis `axis` */
+typedef struct plbm_shape {
+  int32_t kind;
+  int32_t axis;
+  double rho_in, rho_out; /* liquid and vapour densities */
+  double W;               /* interface width parameter */
+  double R;               /* droplet radius */
+  double centre[3];       /* droplet centre */
+  double level;           /* layer height */
+  double u0[3];           /* uniform initial velocity */
+} plbm_shape;
+
+/* Global diagnostics of one lattice at its current time. */
+typedef struct plbm_diag {
+  double mass;            /* sum rho, compensated float64 sum */
+  double mass_comp_err;   /* magnitude of the compensation term */
+  double momentum[3];     /* sum rho u (u includes F/2, eq. Momentum) */
+  double max_u;           /* max |u| */
+  double max_du_per_step; /* max |u(t) - u(t_prev)| / (t - t_prev) since the previous
+                             plbm_reduce on this lattice (0 on the first call) */
+  int64_t time;           /* steps taken */
+  int32_t flags;          /* PLBM_FLAG_* */
+  int32_t pad0;
+} plbm_diag;
+
+typedef struct plbm_lattice plbm_lattice;
+typedef struct plbm_batch plbm_batch;
+
+/* ABI version of the loaded library (PLBM_ABI_VERSION). */
+int plbm_abi_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* plbm_last_error(void);
+
+/* Unit conversion and parameter derivation (host only, float64).
+ * eqs. (unit), (unit2): conversion factors from L_phs/L_lat, tau_l and
+ * rho_l,lat; eq. (thickness): K = p_c/rho_c^3 from the interface width xi;
+ * eq. (surface_tension): kappa from gamma (f_gamma with rho_v, rho_l as in
+ * Appendix B); tau_v from nu_v; body force / C_VF.  For Peng-Robinson the
+ * lattice EOS is fixed by T_over_Tc and omega, and rho_v, rho_l are solved
+ * from the mechanical-stability condition.
+ * Errors: PLBM_E_INVALID (rho_v >= rho_l, tau_l <= 1/2, xi <= 0, L <= 0, ...),
+ * PLBM_E_NOCONVERGE (root solve). */
+int plbm_resolve_params(const plbm_phys_params* phys, const plbm_lattice_map* map, plbm_lattice_params* out);
+
+/* Lattice-unit Peng-Robinson parameters (Yuan-Schaefer constants) at
+ * T/Tc and acentric factor omega; rho_v, rho_l from the mechanical-stability
+ * condition of Sec. IV at this epsilon.  body_force may be NULL. */
+int plbm_params_pr_lattice(double T_over_Tc, double omega, double epsilon, double kappa, double tau_v,
+                           double tau_l, const double* body_force, plbm_lattice_params* out);
+
+/* Lattice-unit paper-EOS parameters: eq. (EOS) with coexistence rho_v, rho_l
+ * and K from the width xi (eq. thickness); rho_v/rho_l of the output are the
+ * finite-psi mechanical-stability prediction at this epsilon.
+ * body_force may be NULL. */
+int plbm_params_paper_lattice(double rho_v, double rho_l, double xi, double epsilon, double kappa,
+                              double tau_v, double tau_l, const double* body_force, plbm_lattice_params* out);
+
+/* Exact device bytes plbm_create needs for this descriptor: two population
+ * arrays (A-B pattern), float64 staging for moments/fields, the previous
+ * velocity for the convergence residual, reduction partials. */
+int plbm_lattice_bytes(const plbm_lattice_desc* desc, uint64_t* bytes);
+
+/* Bind a lattice to caller-owned device memory dev_mem (at least
+ * plbm_lattice_bytes bytes, 256-byte aligned, must outlive the lattice) and a
+ * caller-owned HIP stream (hipStream_t, may be NULL for the null stream).
+ * The populations are undefined until plbm_init_* or plbm_write_populations.
+ * Errors: PLBM_E_INVALID, PLBM_E_NOMEM (dev_bytes too small),
+ * PLBM_E_UNSUPPORTED (walls on an axis other than the last). */
+int plbm_create(const plbm_lattice_desc* desc, const plbm_lattice_params* params, void* dev_mem,
+                uint64_t dev_bytes, void* hip_stream, plbm_lattice** out);
+
+/* f = f_eq(rho, u) (eq. Single_Phase_EDF) from host float64 fields rho[N] and
+ * u[d][N] (u may be NULL: u = 0); resets time to 0.  Synchronises the stream. */
+int plbm_init_fields(plbm_lattice* lat, const double* rho, const double* u);
+
+/* f = f_eq of a density shape evaluated on the device; resets time to 0. */
+int plbm_init_shape(plbm_lattice* lat, const plbm_shape* shape);
+
+/* Enqueue n update steps on the lattice's stream; returns without waiting. */
+int plbm_step(plbm_lattice* lat, int64_t n);
+
+/* rho[N] and u[d][N] at the current time (u includes F/2, eq. Momentum),
+ * copied into host float64 buffers.  Synchronises the stream. */
+int plbm_read_moments(plbm_lattice* lat, double* rho, double* u);
+
+/* Same as plbm_read_moments into caller device buffers (float64), enqueued
+ * on the lattice's stream without waiting. */
+int plbm_moments_device(plbm_lattice* lat, void* rho_dev, void* u_dev);
+
+/* Post-streaming populations f_i(x, t) at the current time, decoded to
+ * float64, host layout f[q][...].  Synchronises the stream. */
+int plbm_read_populations(plbm_lattice* lat, double* f);
+
+/* Replace the state by host float64 populations f[q][...] (checkpoint
+ * restore, fault injection).  Time is left unchanged.  Synchronises. */
+int plbm_write_populations(plbm_lattice* lat, const double* f);
+
+/* Steps taken since the last initialisation. */
+int plbm_get_time(plbm_lattice* lat, int64_t* t);
+
+/* Global diagnostics at the current time; stores u for the next residual.
+ * Synchronises the stream.  Returns PLBM_E_UNSTABLE (with *out filled) when
+ * the NaN or rho <= 0 flag is raised. */
+int plbm_reduce(plbm_lattice* lat, plbm_diag* out);
+
+/* Release the handle (not the caller's device memory). */
+void plbm_destroy(plbm_lattice* lat);
+
+/* Continuous batching of lattices that share a lattice kind, collision,
+ * storage and boundary kinds ("type").  max_slots bounds the number attached
+ * at once.  The batch owns no lattice memory; its slot table lives in a
+ * caller-owned device buffer of plbm_batch_bytes(max_slots, max_tiles) bytes.
+ * Each plbm_batch_step(n) enqueues n steps of every attached lattice as one
+ * launch per step covering all slots; attach/detach rewrite the device slot
+ * table only.  Results are bitwise identical to stepping each lattice alone. */
+int plbm_batch_bytes(int32_t max_slots, int64_t max_tiles, uint64_t* bytes);
+int plbm_batch_create(int32_t max_slots, int64_t max_tiles, void* dev_mem, uint64_t dev_bytes, void* hip_stream,
+                      plbm_batch** out);
+int plbm_batch_attach(plbm_batch* b, plbm_lattice* lat, int32_t* slot);
+int plbm_batch_detach(plbm_batch* b, int32_t slot);
+int plbm_batch_step(plbm_batch* b, int64_t n);
+int plbm_batch_diag(plbm_batch* b, plbm_diag* per_slot); /* per_slot[max_slots]; unused slots zeroed */
+void plbm_batch_destroy(plbm_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PLBM_H */

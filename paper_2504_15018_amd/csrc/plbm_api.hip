@@ -1,0 +1,713 @@
+// C ABI of libplbm (declared in include/plbm.h): lattice handles bound to
+// caller-owned device memory, kernel launches on the caller's stream, and the
+// continuous-batching slot table.
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "plbm_aux.hpp"
+#include "plbm_host.hpp"
+#include "plbm_launch.hpp"
+
+using namespace plbm;
+
+namespace plbm {
+
+static thread_local std::string g_err;
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+}  // namespace plbm
+
+#define HIPCHK(x)                                                                              \
+  do {                                                                                         \
+    hipError_t e_ = (x);                                                                       \
+    if (e_ != hipSuccess) return set_error(PLBM_E_DEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int storage_bytes(int storage) { return storage == PLBM_F64 ? 8 : storage == PLBM_F32 ? 4 : 2; }
+
+struct Layout {
+  int Q, D;
+  int nxk, nyk, nzk;  // kernel axes
+  int tx, ty, cz, tiles_x, tiles_y, tiles_z, ntiles;
+  int64_t N;
+  uint64_t popA, popB, aux, uprev, red, kp, total;
+};
+
+int choose_cz(int nzk, int tiles_xy) {
+  if (const char* e = std::getenv("PLBM_CZ")) {
+    int v = std::atoi(e);
+    if (v > 0) return v < nzk ? v : nzk;
+  }
+  int64_t target = 1024;
+  int64_t cz = ((int64_t)nzk * tiles_xy + target - 1) / target;
+  if (cz < 4) cz = 4;
+  if (cz > 64) cz = 64;
+  if (cz > nzk) cz = nzk;
+  return (int)cz;
+}
+
+int make_layout(const plbm_lattice_desc* d, Layout* L) {
+  if (!d) return set_error(PLBM_E_INVALID, "null descriptor");
+  if (d->lattice != PLBM_D2Q9 && d->lattice != PLBM_D3Q19) return set_error(PLBM_E_INVALID, "unknown lattice kind");
+  if (d->collision != PLBM_BGK && d->collision != PLBM_MRT) return set_error(PLBM_E_INVALID, "unknown collision");
+  if (d->storage < PLBM_F64 || d->storage > PLBM_BF16S) return set_error(PLBM_E_INVALID, "unknown storage");
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) return set_error(PLBM_E_INVALID, "lattice sizes must be >= 1");
+  const bool is2d = d->lattice == PLBM_D2Q9;
+  if (is2d && d->nz != 1) return set_error(PLBM_E_INVALID, "D2Q9 requires nz = 1");
+  for (int a = 0; a < 3; ++a)
+    if (d->bc[a] != PLBM_PERIODIC && d->bc[a] != PLBM_HALFWAY_BB) return set_error(PLBM_E_INVALID, "unknown boundary kind");
+  const int last = is2d ? 1 : 2;
+  for (int a = 0; a < 3; ++a)
+    if (a != last && d->bc[a] != PLBM_PERIODIC)
+      return set_error(PLBM_E_UNSUPPORTED, "walls are supported on the last axis only (axis %d given)", a);
+  L->Q = is2d ? 9 : 19;
+  L->D = is2d ? 2 : 3;
+  L->nxk = d->nx;
+  L->nyk = is2d ? 1 : d->ny;
+  L->nzk = is2d ? d->ny : d->nz;
+  L->N = (int64_t)d->nx * d->ny * d->nz;
+  if (L->N > 0x7fffffffLL) return set_error(PLBM_E_INVALID, "lattice larger than 2^31 - 1 nodes");
+  L->tx = is2d ? TileShape<D2Q9L>::TX : TileShape<D3Q19L>::TX;
+  L->ty = is2d ? TileShape<D2Q9L>::TY : TileShape<D3Q19L>::TY;
+  L->tiles_x = (L->nxk + L->tx - 1) / L->tx;
+  L->tiles_y = (L->nyk + L->ty - 1) / L->ty;
+  L->cz = choose_cz(L->nzk, L->tiles_x * L->tiles_y);
+  L->tiles_z = (L->nzk + L->cz - 1) / L->cz;
+  int64_t nt = (int64_t)L->tiles_x * L->tiles_y * L->tiles_z;
+  if (nt > 0x3fffffff) return set_error(PLBM_E_INVALID, "too many tiles");
+  L->ntiles = (int)nt;
+  const uint64_t S = storage_bytes(d->storage);
+  uint64_t off = 0;
+  L->popA = off;
+  off = align_up(off + (uint64_t)L->Q * L->N * S);
+  L->popB = off;
+  off = align_up(off + (uint64_t)L->Q * L->N * S);
+  L->aux = off;
+  off = align_up(off + 4ull * L->N * 8);
+  L->uprev = off;
+  off = align_up(off + (uint64_t)L->D * L->N * 4);
+  L->red = off;
+  off = align_up(off + (uint64_t)(L->ntiles + 1) * sizeof(RedRec));
+  L->kp = off;
+  off = align_up(off + sizeof(KParams));
+  L->total = off;
+  return PLBM_OK;
+}
+
+}  // namespace
+
+struct plbm_lattice {
+  plbm_lattice_desc desc;
+  plbm_lattice_params prm;
+  Layout lay;
+  KParams kp;
+  KParams* kp_dev;
+  hipStream_t stream;
+  char* mem;
+  int64_t t;
+  int64_t t_red;
+  bool has_red;
+  hipGraphExec_t graph2;  // two steps (phase 0, phase 1)
+  bool has_graph;
+};
+
+namespace {
+
+hipError_t launch_step(const plbm_lattice_desc& d, StepLaunch& a) {
+  switch (d.storage) {
+    case PLBM_F64: return launch_step_f64(a);
+    case PLBM_F32: return launch_step_f32(a);
+    case PLBM_F16S: return launch_step_f16s(a);
+    default: return launch_step_bf16s(a);
+  }
+}
+
+hipError_t launch_aux(const plbm_lattice_desc& d, AuxLaunch& a) {
+  switch (d.storage) {
+    case PLBM_F64: return launch_aux_f64(a);
+    case PLBM_F32: return launch_aux_f32(a);
+    case PLBM_F16S: return launch_aux_f16s(a);
+    default: return launch_aux_bf16s(a);
+  }
+}
+
+int aux_blocks(int64_t N) {
+  int64_t b = (N + 255) / 256;
+  return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+}
+
+int run_step_kernel(plbm_lattice* L, int mode, int phase, double* orho, double* ou) {
+  StepLaunch a{};
+  a.lattice = L->desc.lattice;
+  a.coll = L->desc.collision;
+  a.mode = mode;
+  a.nblocks = L->lay.ntiles;
+  a.stream = L->stream;
+  a.P = L->kp_dev;
+  a.work = nullptr;
+  a.nwork = 0;
+  a.phase = phase;
+  a.out_rho = orho;
+  a.out_u = ou;
+  HIPCHK(launch_step(L->desc, a));
+  return PLBM_OK;
+}
+
+int run_aux(plbm_lattice* L, int what, int dir, const double* in0, const double* in1, double* out,
+            const ShapeK* shape) {
+  AuxLaunch a{};
+  a.lattice = L->desc.lattice;
+  a.what = what;
+  a.nblocks = aux_blocks(L->lay.N);
+  a.stream = L->stream;
+  a.P = L->kp_dev;
+  a.par = (int)(L->t & 1);
+  a.dir = dir;
+  a.in0 = in0;
+  a.in1 = in1;
+  a.out = out;
+  a.shape = shape;
+  HIPCHK(launch_aux(L->desc, a));
+  return PLBM_OK;
+}
+
+double* aux_ptr(plbm_lattice* L) { return reinterpret_cast<double*>(L->mem + L->lay.aux); }
+
+void fill_kparams(plbm_lattice* L) {
+  const Layout& y = L->lay;
+  const plbm_lattice_params& p = L->prm;
+  KParams& k = L->kp;
+  std::memset(&k, 0, sizeof(k));
+  k.pop[0] = L->mem + y.popA;
+  k.pop[1] = L->mem + y.popB;
+  k.aux = reinterpret_cast<double*>(L->mem + y.aux);
+  k.uprev = reinterpret_cast<float*>(L->mem + y.uprev);
+  k.red = reinterpret_cast<double*>(L->mem + y.red);
+  k.N = y.N;
+  k.nx = y.nxk;
+  k.ny = y.nyk;
+  k.nz = y.nzk;
+  k.bb_z = L->desc.bc[L->desc.lattice == PLBM_D2Q9 ? 1 : 2] == PLBM_HALFWAY_BB;
+  k.tiles_x = y.tiles_x;
+  k.tiles_y = y.tiles_y;
+  k.tiles_z = y.tiles_z;
+  k.cz = y.cz;
+  k.ntiles = y.ntiles;
+  k.eos = p.eos;
+  k.K = p.K;
+  k.e_rv = p.eos_rho_v;
+  k.e_rl = p.eos_rho_l;
+  k.e_sqrt_rv = std::sqrt(p.eos_rho_v);
+  k.pr_RT = p.pr_R * p.pr_T;
+  k.pr_b = p.pr_b;
+  k.pr_aalpha = p.pr_a * p.pr_alpha;
+  k.eps = p.epsilon;
+  k.kappa = p.kappa;
+  k.G = p.G;
+  k.tau_v = p.tau_v;
+  k.tau_slope = (p.tau_l - p.tau_v) / (p.rho_l - p.rho_v);
+  k.rho_v = p.rho_v;
+  for (int a = 0; a < 3; ++a) k.Fg[a] = p.body_force[a];
+  const double defaults[4] = {0.8, 0.8, 1.1, 1.1};
+  for (int a = 0; a < 4; ++a) k.rates[a] = L->desc.mrt_rates[a] > 0 ? L->desc.mrt_rates[a] : defaults[a];
+  k.rho0_shift = (L->desc.storage == PLBM_F16S || L->desc.storage == PLBM_BF16S)
+                     ? (L->desc.rho0_shift > 0 ? L->desc.rho0_shift : p.rho_l)
+                     : 0.0;
+  k.parity = 0;
+}
+
+int check_lat(plbm_lattice* L) { return L ? PLBM_OK : set_error(PLBM_E_INVALID, "null lattice"); }
+
+int capture_graph2(plbm_lattice* L) {
+  if (L->has_graph) return PLBM_OK;
+  hipGraph_t g;
+  HIPCHK(hipStreamBeginCapture(L->stream, hipStreamCaptureModeThreadLocal));
+  int st = run_step_kernel(L, MODE_STEP, 0, nullptr, nullptr);
+  if (st == PLBM_OK) st = run_step_kernel(L, MODE_STEP, 1, nullptr, nullptr);
+  hipError_t e = hipStreamEndCapture(L->stream, &g);
+  if (st != PLBM_OK) return st;
+  if (e != hipSuccess) return set_error(PLBM_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&L->graph2, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return set_error(PLBM_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  L->has_graph = true;
+  return PLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int plbm_abi_version(void) { return PLBM_ABI_VERSION; }
+
+const char* plbm_last_error(void) { return g_err.c_str(); }
+
+int plbm_resolve_params(const plbm_phys_params* phys, const plbm_lattice_map* map, plbm_lattice_params* out) {
+  return params_resolve(phys, map, out);
+}
+
+int plbm_params_pr_lattice(double T_over_Tc, double omega, double epsilon, double kappa, double tau_v, double tau_l,
+                           const double* body_force, plbm_lattice_params* out) {
+  if (!out) return set_error(PLBM_E_INVALID, "null output");
+  return params_pr_lattice(T_over_Tc, omega, epsilon, kappa, tau_v, tau_l, body_force, out);
+}
+
+int plbm_params_paper_lattice(double rho_v, double rho_l, double xi, double epsilon, double kappa, double tau_v,
+                              double tau_l, const double* body_force, plbm_lattice_params* out) {
+  if (!out) return set_error(PLBM_E_INVALID, "null output");
+  return params_paper_lattice(rho_v, rho_l, xi, epsilon, kappa, tau_v, tau_l, body_force, out);
+}
+
+int plbm_lattice_bytes(const plbm_lattice_desc* desc, uint64_t* bytes) {
+  if (!bytes) return set_error(PLBM_E_INVALID, "null output");
+  Layout L;
+  int st = make_layout(desc, &L);
+  if (st) return st;
+  *bytes = L.total;
+  return PLBM_OK;
+}
+
+int plbm_create(const plbm_lattice_desc* desc, const plbm_lattice_params* params, void* dev_mem, uint64_t dev_bytes,
+                void* hip_stream, plbm_lattice** out) {
+  if (!out || !params) return set_error(PLBM_E_INVALID, "null argument");
+  *out = nullptr;
+  Layout lay;
+  int st = make_layout(desc, &lay);
+  if (st) return st;
+  if (!dev_mem) return set_error(PLBM_E_INVALID, "null device memory");
+  if (((uintptr_t)dev_mem) % kAlign) return set_error(PLBM_E_INVALID, "device memory must be 256-byte aligned");
+  if (dev_bytes < lay.total)
+    return set_error(PLBM_E_NOMEM, "device buffer holds %llu bytes, lattice needs %llu", (unsigned long long)dev_bytes,
+                     (unsigned long long)lay.total);
+  if (!(params->rho_l > params->rho_v) || !(params->tau_v > 0.5) || !(params->tau_l > 0.5))
+    return set_error(PLBM_E_INVALID, "parameters: need rho_v < rho_l and tau > 1/2");
+  if (params->eos != PLBM_EOS_PAPER && params->eos != PLBM_EOS_PENG_ROBINSON)
+    return set_error(PLBM_E_INVALID, "parameters: unknown EOS");
+  plbm_lattice* L = new plbm_lattice();
+  L->desc = *desc;
+  L->prm = *params;
+  L->lay = lay;
+  L->mem = static_cast<char*>(dev_mem);
+  L->stream = static_cast<hipStream_t>(hip_stream);
+  L->t = 0;
+  L->t_red = 0;
+  L->has_red = false;
+  L->has_graph = false;
+  L->kp_dev = reinterpret_cast<KParams*>(L->mem + lay.kp);
+  fill_kparams(L);
+  hipError_t e = hipMemcpyAsync(L->kp_dev, &L->kp, sizeof(KParams), hipMemcpyHostToDevice, L->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(L->mem + lay.uprev, 0, (size_t)lay.D * lay.N * 4, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) {
+    delete L;
+    return set_error(PLBM_E_DEVICE, "plbm_create: %s", hipGetErrorString(e));
+  }
+  *out = L;
+  return PLBM_OK;
+}
+
+int plbm_init_fields(plbm_lattice* L, const double* rho, const double* u) {
+  if (check_lat(L)) return PLBM_E_INVALID;
+  if (!rho) return set_error(PLBM_E_INVALID, "null rho");
+  const int64_t N = L->lay.N;
+  double* aux = aux_ptr(L);
+  HIPCHK(hipMemcpyAsync(aux, rho, N * 8, hipMemcpyHostToDevice, L->stream));
+  if (u) HIPCHK(hipMemcpyAsync(aux + N, u, (size_t)L->lay.D * N * 8, hipMemcpyHostToDevice, L->stream));
+  L->t = 0;
+  L->has_red = false;
+  int st = run_aux(L, AUX_INIT_FIELDS, 0, aux, u ? aux + N : nullptr, nullptr, nullptr);
+  if (st) return st;
+  HIPCHK(hipStreamSynchronize(L->stream));
+  return PLBM_OK;
+}
+
+int plbm_init_shape(plbm_lattice* L, const plbm_shape* s) {
+  if (check_lat(L)) return PLBM_E_INVALID;
+  if (!s || s->kind < 0 || s->kind > 2 || !(s->W > 0)) return set_error(PLBM_E_INVALID, "bad shape");
+  if (s->axis < 0 || s->axis >= L->lay.D) return set_error(PLBM_E_INVALID, "shape axis out of range");
+  ShapeK k;
+  k.kind = s->kind;
+  k.axis = s->axis;
+  k.rho_in = s->rho_in;
+  k.rho_out = s->rho_out;
+  k.W = s->W;
+  k.R = s->R;
+  for (int a = 0; a < 3; ++a) {
+    k.centre[a] = s->centre[a];
+    k.u0[a] = a < L->lay.D ? s->u0[a] : 0.0;
+  }
+  k.level = s->level;
+  L->t = 0;
+  L->has_red = false;
+  int st = run_aux(L, AUX_INIT_SHAPE, 0, nullptr, nullptr, nullptr, &k);
+  if (st) return st;
+  HIPCHK(hipStreamSynchronize(L->stream));
+  return PLBM_OK;
+}
+
+int plbm_step(plbm_lattice* L, int64_t n) {
+  if (check_lat(L)) return PLBM_E_INVALID;
+  if (n < 0) return set_error(PLBM_E_INVALID, "negative step count");
+  // long runs replay a captured two-step graph; short ones launch directly
+  // (the legacy null stream cannot be captured)
+  if (n >= 8 && L->stream != nullptr && !std::getenv("PLBM_NO_GRAPH")) {
+    int st = capture_graph2(L);
+    if (st) return st;
+    if (L->t & 1) {
+      st = run_step_kernel(L, MODE_STEP, 1, nullptr, nullptr);
+      if (st) return st;
+      ++L->t;
+      --n;
+    }
+    for (; n >= 2; n -= 2) {
+      HIPCHK(hipGraphLaunch(L->graph2, L->stream));
+      L->t += 2;
+    }
+  }
+  for (; n > 0; --n) {
+    int st = run_step_kernel(L, MODE_STEP, (int)(L->t & 1), nullptr, nullptr);
+    if (st) return st;
+    ++L->t;
+  }
+  return PLBM_OK;
+}
+
+int plbm_moments_device(plbm_lattice* L, void* rho_dev, void* u_dev) {
+  if (check_lat(L)) return PLBM_E_INVALID;
+  if (!rho_dev || !u_dev) return set_error(PLBM_E_INVALID, "null output");
+  return run_step_kernel(L, MODE_MOMENTS, (int)(L->t & 1), static_cast<double*>(rho_dev), static_cast<double*>(u_dev));
+}
+
+int plbm_read_moments(plbm_lattice* L, double* rho, double* u) {
+  if (check_lat(L)) return PLBM_E_INVALID;
+  if (!rho || !u) return set_error(PLBM_E_INVALID, "null output");
+  const int64_t N = L->lay.N;
+  double* aux = aux_ptr(L);
+  int st = run_step_kernel(L, MODE_MOMENTS, (int)(L->t & 1), aux, aux + N);
+  if (st) return st;
+  HIPCHK(hipMemcpyAsync(rho, aux, N * 8, hipMemcpyDeviceToHost, L->stream));
+  HIPCHK(hipMemcpyAsync(u, aux + N, (size_t)L->lay.D * N * 8, hipMemcpyDeviceToHost, L->stream));
+  HIPCHK(hipStreamSynchronize(L->stream));
+  return PLBM_OK;
+}
+
+int plbm_read_populations(plbm_lattice* L, double* f) {
+  if (check_lat(L)) return PLBM_E_INVALID;
+  if (!f) return set_error(PLBM_E_INVALID, "null output");
+  const int64_t N = L->lay.N;
+  double* aux = aux_ptr(L);
+  for (int q = 0; q < L->lay.Q; ++q) {
+    int st = run_aux(L, AUX_READ_POP, q, nullptr, nullptr, aux, nullptr);
+    if (st) return st;
+    HIPCHK(hipMemcpyAsync(f + (size_t)q * N, aux, N * 8, hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+  }
+  return PLBM_OK;
+}
+
+int plbm_write_populations(plbm_lattice* L, const double* f) {
+  if (check_lat(L)) return PLBM_E_INVALID;
+  if (!f) return set_error(PLBM_E_INVALID, "null input");
+  const int64_t N = L->lay.N;
+  double* aux = aux_ptr(L);
+  for (int q = 0; q < L->lay.Q; ++q) {
+    HIPCHK(hipMemcpyAsync(aux, f + (size_t)q * N, N * 8, hipMemcpyHostToDevice, L->stream));
+    int st = run_aux(L, AUX_WRITE_POP, q, aux, nullptr, nullptr, nullptr);
+    if (st) return st;
+    HIPCHK(hipStreamSynchronize(L->stream));
+  }
+  return PLBM_OK;
+}
+
+int plbm_get_time(plbm_lattice* L, int64_t* t) {
+  if (check_lat(L)) return PLBM_E_INVALID;
+  if (!t) return set_error(PLBM_E_INVALID, "null output");
+  *t = L->t;
+  return PLBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+void fill_diag(plbm_lattice* L, const RedRec& r, plbm_diag* out) {
+  std::memset(out, 0, sizeof(*out));
+  out->mass = r.mass_s + r.mass_c;
+  out->mass_comp_err = std::fabs(r.mass_c);
+  for (int a = 0; a < 3; ++a) out->momentum[a] = r.mom[a];
+  out->max_u = r.max_u;
+  out->max_du_per_step = (L->has_red && L->t > L->t_red) ? r.max_du / (double)(L->t - L->t_red) : 0.0;
+  out->time = L->t;
+  out->flags = (int)r.flags;
+  L->t_red = L->t;
+  L->has_red = true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int plbm_reduce(plbm_lattice* L, plbm_diag* out) {
+  if (check_lat(L)) return PLBM_E_INVALID;
+  if (!out) return set_error(PLBM_E_INVALID, "null output");
+  int st = run_step_kernel(L, MODE_REDUCE, (int)(L->t & 1), nullptr, nullptr);
+  if (st) return st;
+  RedRec* fin = reinterpret_cast<RedRec*>(L->mem + L->lay.red) + L->lay.ntiles;
+  HIPCHK(launch_reduce_final(L->stream, L->kp_dev, L->lay.ntiles, fin));
+  RedRec r;
+  HIPCHK(hipMemcpyAsync(&r, fin, sizeof(r), hipMemcpyDeviceToHost, L->stream));
+  HIPCHK(hipStreamSynchronize(L->stream));
+  fill_diag(L, r, out);
+  if (out->flags & (PLBM_FLAG_NAN | PLBM_FLAG_RHO_NONPOS))
+    return set_error(PLBM_E_UNSTABLE, "lattice unstable (flags 0x%x at t = %lld)", out->flags, (long long)L->t);
+  return PLBM_OK;
+}
+
+void plbm_destroy(plbm_lattice* L) {
+  if (!L) return;
+  if (L->has_graph) hipGraphExecDestroy(L->graph2);
+  delete L;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// continuous batching
+
+struct plbm_batch {
+  int max_slots;
+  int64_t max_tiles;
+  char* mem;
+  hipStream_t stream;
+  KParams* slots_dev;
+  WorkItem* work_dev;
+  std::vector<plbm_lattice*> lat;
+  struct Group {
+    int lattice, coll, storage;
+    int offset, count;  // segment of the work table
+  };
+  std::vector<Group> groups;
+  std::vector<KParams> slots_host;
+  std::vector<WorkItem> work_host;
+  int64_t g;  // steps since the last rebuild
+  bool dirty;
+  hipGraphExec_t graph2;
+  bool has_graph;
+};
+
+namespace {
+
+uint64_t batch_layout(int max_slots, int64_t max_tiles, uint64_t* off_work) {
+  uint64_t off = align_up((uint64_t)max_slots * sizeof(KParams));
+  *off_work = off;
+  off = align_up(off + (uint64_t)max_tiles * sizeof(WorkItem));
+  return off;
+}
+
+int batch_rebuild(plbm_batch* b) {
+  if (!b->dirty) return PLBM_OK;
+  if (b->has_graph) {
+    hipGraphExecDestroy(b->graph2);
+    b->has_graph = false;
+  }
+  b->groups.clear();
+  b->work_host.clear();
+  std::map<std::tuple<int, int, int>, std::vector<int>> by_type;
+  for (int s = 0; s < b->max_slots; ++s) {
+    plbm_lattice* L = b->lat[s];
+    if (!L) continue;
+    KParams k = L->kp;
+    k.parity = (int)(L->t & 1);
+    b->slots_host[s] = k;
+    by_type[std::make_tuple(L->desc.lattice, L->desc.collision, L->desc.storage)].push_back(s);
+  }
+  for (auto& kv : by_type) {
+    plbm_batch::Group gr;
+    gr.lattice = std::get<0>(kv.first);
+    gr.coll = std::get<1>(kv.first);
+    gr.storage = std::get<2>(kv.first);
+    gr.offset = (int)b->work_host.size();
+    for (int s : kv.second)
+      for (int t = 0; t < b->lat[s]->lay.ntiles; ++t) b->work_host.push_back(WorkItem{s, t});
+    gr.count = (int)b->work_host.size() - gr.offset;
+    b->groups.push_back(gr);
+  }
+  if ((int64_t)b->work_host.size() > b->max_tiles)
+    return set_error(PLBM_E_NOMEM, "batch work table holds %lld tiles, %zu needed", (long long)b->max_tiles,
+                     b->work_host.size());
+  HIPCHK(hipMemcpyAsync(b->slots_dev, b->slots_host.data(), sizeof(KParams) * b->max_slots, hipMemcpyHostToDevice,
+                        b->stream));
+  if (!b->work_host.empty())
+    HIPCHK(hipMemcpyAsync(b->work_dev, b->work_host.data(), sizeof(WorkItem) * b->work_host.size(),
+                          hipMemcpyHostToDevice, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  b->g = 0;
+  b->dirty = false;
+  return PLBM_OK;
+}
+
+int batch_launch(plbm_batch* b, int mode, int phase) {
+  for (auto& gr : b->groups) {
+    StepLaunch a{};
+    a.lattice = gr.lattice;
+    a.coll = gr.coll;
+    a.mode = mode;
+    a.nblocks = gr.count;
+    a.stream = b->stream;
+    a.P = b->slots_dev;
+    a.work = b->work_dev + gr.offset;
+    a.nwork = gr.count;
+    a.phase = phase;
+    plbm_lattice_desc d{};
+    d.storage = gr.storage;
+    HIPCHK(launch_step(d, a));
+  }
+  return PLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int plbm_batch_bytes(int32_t max_slots, int64_t max_tiles, uint64_t* bytes) {
+  if (max_slots < 1 || max_tiles < 1 || !bytes) return set_error(PLBM_E_INVALID, "bad batch sizes");
+  uint64_t ow;
+  *bytes = batch_layout(max_slots, max_tiles, &ow);
+  return PLBM_OK;
+}
+
+int plbm_batch_create(int32_t max_slots, int64_t max_tiles, void* dev_mem, uint64_t dev_bytes, void* hip_stream,
+                      plbm_batch** out) {
+  if (!out || max_slots < 1 || max_tiles < 1 || !dev_mem) return set_error(PLBM_E_INVALID, "bad batch arguments");
+  if (((uintptr_t)dev_mem) % kAlign) return set_error(PLBM_E_INVALID, "device memory must be 256-byte aligned");
+  uint64_t ow;
+  uint64_t need = batch_layout(max_slots, max_tiles, &ow);
+  if (dev_bytes < need) return set_error(PLBM_E_NOMEM, "batch needs %llu bytes", (unsigned long long)need);
+  plbm_batch* b = new plbm_batch();
+  b->max_slots = max_slots;
+  b->max_tiles = max_tiles;
+  b->mem = static_cast<char*>(dev_mem);
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->slots_dev = reinterpret_cast<KParams*>(b->mem);
+  b->work_dev = reinterpret_cast<WorkItem*>(b->mem + ow);
+  b->lat.assign(max_slots, nullptr);
+  b->slots_host.assign(max_slots, KParams{});
+  b->g = 0;
+  b->dirty = true;
+  b->has_graph = false;
+  *out = b;
+  return PLBM_OK;
+}
+
+int plbm_batch_attach(plbm_batch* b, plbm_lattice* L, int32_t* slot) {
+  if (!b || !L || !slot) return set_error(PLBM_E_INVALID, "null argument");
+  for (int s = 0; s < b->max_slots; ++s)
+    if (b->lat[s] == L) return set_error(PLBM_E_INVALID, "lattice already attached");
+  for (int s = 0; s < b->max_slots; ++s) {
+    if (!b->lat[s]) {
+      b->lat[s] = L;
+      b->dirty = true;
+      *slot = s;
+      return PLBM_OK;
+    }
+  }
+  return set_error(PLBM_E_NOMEM, "no free batch slot");
+}
+
+int plbm_batch_detach(plbm_batch* b, int32_t slot) {
+  if (!b || slot < 0 || slot >= b->max_slots || !b->lat[slot]) return set_error(PLBM_E_INVALID, "bad slot");
+  // the lattice keeps its own time; its standalone kernel block has parity 0
+  b->lat[slot] = nullptr;
+  b->dirty = true;
+  return PLBM_OK;
+}
+
+int plbm_batch_step(plbm_batch* b, int64_t n) {
+  if (!b || n < 0) return set_error(PLBM_E_INVALID, "bad batch step");
+  int st = batch_rebuild(b);
+  if (st) return st;
+  if (b->groups.empty()) return PLBM_OK;
+  const int64_t n0 = n;
+  if (n >= 4 && b->stream != nullptr && !std::getenv("PLBM_NO_GRAPH")) {
+    if (!b->has_graph) {
+      hipGraph_t gr;
+      HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      int s1 = batch_launch(b, MODE_STEP, 0);
+      if (s1 == PLBM_OK) s1 = batch_launch(b, MODE_STEP, 1);
+      hipError_t e = hipStreamEndCapture(b->stream, &gr);
+      if (s1) return s1;
+      if (e != hipSuccess) return set_error(PLBM_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+      e = hipGraphInstantiate(&b->graph2, gr, nullptr, nullptr, 0);
+      hipGraphDestroy(gr);
+      if (e != hipSuccess) return set_error(PLBM_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      b->has_graph = true;
+    }
+    if (b->g & 1) {
+      st = batch_launch(b, MODE_STEP, 1);
+      if (st) return st;
+      ++b->g;
+      --n;
+    }
+    for (; n >= 2; n -= 2) {
+      HIPCHK(hipGraphLaunch(b->graph2, b->stream));
+      b->g += 2;
+    }
+  }
+  for (; n > 0; --n) {
+    st = batch_launch(b, MODE_STEP, (int)(b->g & 1));
+    if (st) return st;
+    ++b->g;
+  }
+  for (int s = 0; s < b->max_slots; ++s)
+    if (b->lat[s]) b->lat[s]->t += n0;
+  return PLBM_OK;
+}
+
+int plbm_batch_diag(plbm_batch* b, plbm_diag* per_slot) {
+  if (!b || !per_slot) return set_error(PLBM_E_INVALID, "null argument");
+  int st = batch_rebuild(b);
+  if (st) return st;
+  std::memset(per_slot, 0, sizeof(plbm_diag) * b->max_slots);
+  st = batch_launch(b, MODE_REDUCE, (int)(b->g & 1));
+  if (st) return st;
+  std::vector<RedRec> recs(b->max_slots);
+  for (int s = 0; s < b->max_slots; ++s) {
+    plbm_lattice* L = b->lat[s];
+    if (!L) continue;
+    RedRec* fin = reinterpret_cast<RedRec*>(L->mem + L->lay.red) + L->lay.ntiles;
+    HIPCHK(launch_reduce_final(b->stream, L->kp_dev, L->lay.ntiles, fin));
+    HIPCHK(hipMemcpyAsync(&recs[s], fin, sizeof(RedRec), hipMemcpyDeviceToHost, b->stream));
+  }
+  HIPCHK(hipStreamSynchronize(b->stream));
+  for (int s = 0; s < b->max_slots; ++s)
+    if (b->lat[s]) fill_diag(b->lat[s], recs[s], &per_slot[s]);
+  return PLBM_OK;
+}
+
+void plbm_batch_destroy(plbm_batch* b) {
+  if (!b) return;
+  if (b->has_graph) hipGraphExecDestroy(b->graph2);
+  delete b;
+}
+
+}  // extern "C"

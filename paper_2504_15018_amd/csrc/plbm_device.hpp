@@ -1,0 +1,198 @@
+// Device-side definitions shared by every kernel translation unit of libplbm:
+// lattice traits, storage codecs, the pseudo-potential and the kernel
+// parameter block.  gfx950 (CDNA4), wave64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace plbm {
+
+// ---------------------------------------------------------------------------
+// Lattice traits.  Kernel axes are (x, y, z) with x fastest in memory and z the
+// marching axis.  D2Q9 runs as a lattice of extent 1 in y: its second
+// component maps to the marching axis z, so a 2-D lattice (nx, ny) is held as
+// (nx, 1, ny) with the same memory layout f[q][y][x].
+//
+// D2Q9 order is eq. (VelocitySet) of the paper; D3Q19 order: rest, the six
+// axis directions as opposite pairs, the twelve edge directions as pairs.
+
+struct D2Q9L {
+  static constexpr int Q = 9, D = 2, HY = 0;
+  static constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  static constexpr int cy[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  static constexpr int cz[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+  static constexpr double w[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                                  1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+  // physical component a (0: x, 1: y of the 2-D lattice)
+  static constexpr int c(int i, int a) { return a == 0 ? cx[i] : cz[i]; }
+};
+
+struct D3Q19L {
+  static constexpr int Q = 19, D = 3, HY = 1;
+  static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+  static constexpr double w[19] = {1.0 / 3.0,  1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+                                   1.0 / 18.0, 1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                                   1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                                   1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+  static constexpr int c(int i, int a) { return a == 0 ? cx[i] : (a == 1 ? cy[i] : cz[i]); }
+};
+
+// MRT extension: the non-hydrodynamic moments whose rate differs from the
+// stress rate 1/tau(rho).  The collision is written as BGK at omega = 1/tau
+// plus a correction on these moments only:
+//   f* = f + Fhat - omega v - sum_k (s_k - omega) P_k(c_i) (sum_j P_k(c_j) v_j) / |P_k|^2,
+//   v  = f - f_eq + Fhat/2,
+// which equals m* = m - S(m - m_eq) + (I - S/2) M Fhat, f* = M^-1 m* for an
+// orthogonal basis in which the stress moments relax at omega (the mass and
+// momentum rows of M v vanish identically).
+// Moment polynomials (|c|^2 = c2):
+//   D2Q9  (Lallemand-Luo): e = 3c2-4, eps = (9c2^2-21c2+8)/2, q_a = (3c2-5)c_a
+//   D3Q19 (d'Humieres):    e = 19c2-30, eps = (21c2^2-53c2+24)/2, q_a = (5c2-9)c_a,
+//                          m_x = (cy^2-cz^2)cx, m_y = (cz^2-cx^2)cy, m_z = (cx^2-cy^2)cz
+template <class L>
+struct MrtCorr;
+
+template <>
+struct MrtCorr<D2Q9L> {
+  static constexpr int K = 4;  // e, eps, q_x, q_y
+  static constexpr int rate_class[4] = {0, 1, 2, 2};  // index into {s_e, s_eps, s_q, s_m}
+  static constexpr double P(int k, int i) {
+    double cx = D2Q9L::c(i, 0), cy = D2Q9L::c(i, 1), c2 = cx * cx + cy * cy;
+    return k == 0 ? 3 * c2 - 4 : k == 1 ? (9 * c2 * c2 - 21 * c2 + 8) / 2 : k == 2 ? (3 * c2 - 5) * cx : (3 * c2 - 5) * cy;
+  }
+};
+
+template <>
+struct MrtCorr<D3Q19L> {
+  static constexpr int K = 8;  // e, eps, q_x, q_y, q_z, m_x, m_y, m_z
+  static constexpr int rate_class[8] = {0, 1, 2, 2, 2, 3, 3, 3};
+  static constexpr double P(int k, int i) {
+    double cx = D3Q19L::c(i, 0), cy = D3Q19L::c(i, 1), cz = D3Q19L::c(i, 2);
+    double c2 = cx * cx + cy * cy + cz * cz;
+    switch (k) {
+      case 0: return 19 * c2 - 30;
+      case 1: return (21 * c2 * c2 - 53 * c2 + 24) / 2;
+      case 2: return (5 * c2 - 9) * cx;
+      case 3: return (5 * c2 - 9) * cy;
+      case 4: return (5 * c2 - 9) * cz;
+      case 5: return (cy * cy - cz * cz) * cx;
+      case 6: return (cz * cz - cx * cx) * cy;
+      default: return (cx * cx - cy * cy) * cz;
+    }
+  }
+};
+
+template <class L>
+constexpr double mrt_norm(int k) {
+  double s = 0;
+  for (int i = 0; i < L::Q; ++i) s += MrtCorr<L>::P(k, i) * MrtCorr<L>::P(k, i);
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Storage codecs.  Shifted storage keeps f_i - w_i rho0 (one global rho0) so
+// that half-precision formats spend their bits on the deviation from the
+// reference state.
+
+// dec/enc work in the arithmetic type C; dec64/enc64 are the float64 forms
+// used by initialisation and population I/O.
+struct StF64 {
+  using T = double;
+  using C = double;  // arithmetic type
+  static __device__ __forceinline__ C dec(T v, C) { return v; }
+  static __device__ __forceinline__ T enc(C f, C) { return f; }
+  static __device__ __forceinline__ double dec64(T v, double) { return v; }
+  static __device__ __forceinline__ T enc64(double f, double) { return f; }
+};
+
+struct StF32 {
+  using T = float;
+  using C = float;
+  static __device__ __forceinline__ C dec(T v, C) { return v; }
+  static __device__ __forceinline__ T enc(C f, C) { return f; }
+  static __device__ __forceinline__ double dec64(T v, double) { return (double)v; }
+  static __device__ __forceinline__ T enc64(double f, double) { return (float)f; }
+};
+
+struct StF16S {
+  using T = _Float16;
+  using C = float;
+  static __device__ __forceinline__ C dec(T v, C shift) { return (float)v + shift; }
+  static __device__ __forceinline__ T enc(C f, C shift) { return (_Float16)(f - shift); }  // RNE
+  static __device__ __forceinline__ double dec64(T v, double shift) { return (double)(float)v + shift; }
+  static __device__ __forceinline__ T enc64(double f, double shift) { return (_Float16)(float)(f - shift); }
+};
+
+struct StBF16S {
+  using T = uint16_t;  // bfloat16 bit pattern
+  using C = float;
+  static __device__ __forceinline__ C dec(T v, C shift) {
+    return __uint_as_float(((uint32_t)v) << 16) + shift;
+  }
+  static __device__ __forceinline__ T enc(C f, C shift) {
+    float d = f - shift;
+    uint32_t u = __float_as_uint(d);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+  }
+  static __device__ __forceinline__ double dec64(T v, double shift) {
+    return (double)__uint_as_float(((uint32_t)v) << 16) + shift;
+  }
+  static __device__ __forceinline__ T enc64(double f, double shift) { return enc((float)(f - shift), 0.0f); }
+};
+
+// ---------------------------------------------------------------------------
+// Kernel parameter block: one per lattice, resident in device memory (the
+// batch launch reads one per slot).
+
+enum : int32_t { EOS_PAPER = 0, EOS_PR = 1 };
+
+struct KParams {
+  void* pop[2];       // A-B population arrays, each Q*N entries
+  double* aux;        // float64 staging, 4*N
+  float* uprev;       // previous velocity for the residual, D*N
+  double* red;        // reduction partials
+  int64_t N;          // nodes
+  int32_t nx, ny, nz; // kernel axes (2-D lattices: ny = 1)
+  int32_t bb_z;       // half-way bounce-back walls on the marching axis
+  int32_t tiles_x, tiles_y, tiles_z, cz;  // tiling: tiles per axis, planes per z chunk
+  int32_t ntiles;
+  int32_t eos;
+  // paper EOS: p = K [2 r^3 + (rv - 2 rl) r^2 + sqrt(rv) sqrt(r) (-3 r^2 + 2 rl r + rl^2)]
+  double K, e_rv, e_rl, e_sqrt_rv;
+  // Peng-Robinson: p = r R T / (1 - b r) - a alpha r^2 / (1 + 2 b r - b^2 r^2)
+  double pr_RT, pr_b, pr_aalpha;
+  double eps, kappa, G;
+  double tau_v, tau_slope, rho_v;  // tau(rho) = tau_v + (rho - rho_v) tau_slope
+  double Fg[3];
+  double rates[4];                 // s_e, s_eps, s_q, s_m
+  double rho0_shift;
+  int32_t parity;  // batch slots: A-B phase offset of this lattice
+  int32_t pad0;
+};
+
+// psi(rho) of eq. (Interaction_Potential), G = -1, lattice units, float64.
+// Returns the clamped value; *neg is set when the radicand was negative.
+__device__ __forceinline__ double psi_of_rho(const KParams& p, double rho, bool* neg) {
+  double pe;
+  if (p.eos == EOS_PAPER) {
+    double r2 = rho * rho;
+    double s = sqrt(rho);
+    pe = p.K * (2.0 * r2 * rho + (p.e_rv - 2.0 * p.e_rl) * r2 +
+                p.e_sqrt_rv * s * (-3.0 * r2 + 2.0 * p.e_rl * rho + p.e_rl * p.e_rl));
+  } else {
+    double b = p.pr_b;
+    pe = rho * p.pr_RT / (1.0 - b * rho) - p.pr_aalpha * rho * rho / (1.0 + 2.0 * b * rho - b * b * rho * rho);
+  }
+  double rad = 2.0 * (rho / 3.0 - pe);
+  *neg = !(rad >= 0.0);
+  return sqrt(rad > 0.0 ? rad : 0.0);
+}
+
+}  // namespace plbm

@@ -1,0 +1,54 @@
+// Instantiation of every kernel for one storage type.  Included by the
+// per-storage translation units with PLBM_ST (codec) and PLBM_SUFFIX defined.
+#include "plbm_aux.hpp"
+#include "plbm_launch.hpp"
+
+#define PLBM_CAT2(a, b) a##b
+#define PLBM_CAT(a, b) PLBM_CAT2(a, b)
+
+namespace plbm {
+
+template <class L, int COLL, int MODE>
+static hipError_t go_step(const StepLaunch& a) {
+  using TS = TileShape<L>;
+  hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, TS::NT>), dim3(a.nblocks), dim3(TS::NT), 0,
+                     a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
+  return hipGetLastError();
+}
+
+template <class L>
+static hipError_t step_for(const StepLaunch& a) {
+  if (a.mode == MODE_STEP) return a.coll == COLL_MRT ? go_step<L, COLL_MRT, MODE_STEP>(a) : go_step<L, COLL_BGK, MODE_STEP>(a);
+  if (a.mode == MODE_MOMENTS) return go_step<L, COLL_BGK, MODE_MOMENTS>(a);
+  return go_step<L, COLL_BGK, MODE_REDUCE>(a);
+}
+
+hipError_t PLBM_CAT(launch_step_, PLBM_SUFFIX)(const StepLaunch& a) {
+  return a.lattice == 1 ? step_for<D3Q19L>(a) : step_for<D2Q9L>(a);
+}
+
+template <class L>
+static hipError_t aux_for(const AuxLaunch& a) {
+  dim3 g(a.nblocks), b(256);
+  switch (a.what) {
+    case AUX_INIT_FIELDS:
+      hipLaunchKernelGGL((k_init_fields<L, PLBM_ST>), g, b, 0, a.stream, a.P, a.par, a.in0, a.in1);
+      break;
+    case AUX_INIT_SHAPE:
+      hipLaunchKernelGGL((k_init_shape<L, PLBM_ST>), g, b, 0, a.stream, a.P, a.par, *a.shape);
+      break;
+    case AUX_READ_POP:
+      hipLaunchKernelGGL((k_read_pop<L, PLBM_ST>), g, b, 0, a.stream, a.P, a.par, a.dir, a.out);
+      break;
+    default:
+      hipLaunchKernelGGL((k_write_pop<L, PLBM_ST>), g, b, 0, a.stream, a.P, a.par, a.dir, a.in0);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t PLBM_CAT(launch_aux_, PLBM_SUFFIX)(const AuxLaunch& a) {
+  return a.lattice == 1 ? aux_for<D3Q19L>(a) : aux_for<D2Q9L>(a);
+}
+
+}  // namespace plbm

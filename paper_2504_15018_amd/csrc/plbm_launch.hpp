@@ -1,0 +1,69 @@
+// Host-visible launch entry points of the kernel translation units.  Each
+// population storage type is compiled in its own translation unit (the
+// float64 one without floating-point contraction, so that its rounding follows
+// the plain operation order).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "plbm_device.hpp"
+
+namespace plbm {
+
+struct WorkItem;
+struct ShapeK;
+
+// Compile-time tile shapes: D3Q19 32 x 16 nodes per workgroup of 256 threads
+// (2 nodes per thread per plane); D2Q9 rows of 128 nodes per 128 threads.
+template <class L>
+struct TileShape;
+template <>
+struct TileShape<D3Q19L> {
+  static constexpr int TX = 32, TY = 16, NT = 256;
+};
+template <>
+struct TileShape<D2Q9L> {
+  static constexpr int TX = 128, TY = 1, NT = 128;
+};
+
+struct StepLaunch {
+  int lattice;  // 0 D2Q9, 1 D3Q19
+  int coll;     // 0 BGK, 1 MRT
+  int mode;     // 0 step, 1 moments, 2 reduce
+  int nblocks;
+  hipStream_t stream;
+  const KParams* P;
+  const WorkItem* work;
+  int nwork;
+  int phase;
+  double* out_rho;
+  double* out_u;
+};
+
+enum : int { AUX_INIT_FIELDS = 0, AUX_INIT_SHAPE = 1, AUX_READ_POP = 2, AUX_WRITE_POP = 3 };
+
+struct AuxLaunch {
+  int lattice;
+  int what;
+  int nblocks;
+  hipStream_t stream;
+  const KParams* P;
+  int par;
+  int dir;
+  const double* in0;
+  const double* in1;
+  double* out;
+  const ShapeK* shape;
+};
+
+hipError_t launch_step_f64(const StepLaunch&);
+hipError_t launch_step_f32(const StepLaunch&);
+hipError_t launch_step_f16s(const StepLaunch&);
+hipError_t launch_step_bf16s(const StepLaunch&);
+hipError_t launch_aux_f64(const AuxLaunch&);
+hipError_t launch_aux_f32(const AuxLaunch&);
+hipError_t launch_aux_f16s(const AuxLaunch&);
+hipError_t launch_aux_bf16s(const AuxLaunch&);
+hipError_t launch_reduce_final(hipStream_t st, const KParams* P, int ntiles, void* out);
+
+}  // namespace plbm

@@ -1,0 +1,69 @@
+"""Shared set-up for the GPU parity tests: seeded inputs, oracle runs and the
+library runs on the same inputs.  Each side derives its own lattice constants
+from the same primary inputs (T/Tc, omega, eps, kappa, tau_v, tau_l, F_g).
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import plbm_synth as syn
+from oracle import eos as E
+from oracle import params as P
+from oracle import step as S
+from oracle.lattice import LATTICES
+
+
+def require_gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a visible GPU"
+    from paper_2504_15018_amd import native
+    native.load()  # fails loudly when the HIP library is missing
+
+
+@functools.lru_cache(maxsize=None)
+def pr_coex(tr, omega=0.326, eps=2.0):
+    return P.coexistence(E.PengRobinsonEOS(tr, omega), eps)
+
+
+def oracle_params(lattice, tr=0.8, collision="bgk", walls=False, kappa=1.0, tau_v=1.0, tau_l=1.0,
+                  Fg=(0.0, 0.0, 0.0), eps=2.0, rates=None):
+    lat = LATTICES[lattice]
+    rv, rl, _ = pr_coex(tr, 0.326, eps)
+    bc = tuple("bb" if (walls and a == lat.d - 1) else "periodic" for a in range(lat.d))
+    kw = {}
+    if rates is not None:
+        kw["rates"] = rates
+    return S.StepParams(lat, E.PengRobinsonEOS(tr, 0.326), eps=eps, kappa=kappa, tau_v=tau_v, tau_l=tau_l,
+                        rho_v=rv, rho_l=rl, Fg=tuple(Fg[: lat.d]) + (0.0,) * (3 - lat.d), collision=collision,
+                        bc=bc, **kw)
+
+
+def lib_params(tr=0.8, kappa=1.0, tau_v=1.0, tau_l=1.0, Fg=(0.0, 0.0, 0.0), eps=2.0):
+    from paper_2504_15018_amd import native as N
+    return N.plbm_params_pr_lattice(tr, 0.326, eps, kappa, tau_v, tau_l, list(Fg) + [0.0] * (3 - len(Fg)))
+
+
+def random_state(lattice, dims, seed, tr=0.8, rel_amp=0.3):
+    """Positive populations around a droplet density field (non-equilibrium)."""
+    lat = LATTICES[lattice]
+    rv, rl, _ = pr_coex(tr)
+    co = syn.grid(dims)
+    rho = syn.droplet(co, dims, rv, rl, R=min(dims) / 3.0, W=4.0, centre=[n / 2.0 - 0.3 for n in dims])
+    return syn.random_populations(lat.Q, co, dims, seed, rho, rel_amp)
+
+
+def fmt(name, **kw):
+    s = name + " " + " ".join(f"{k}={v}" for k, v in kw.items())
+    print(s, flush=True)
+    sys.stdout.flush()
+    return s
+
+
+def rel_max(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(np.asarray(b))))
+
+
+def abs_max(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))))

@@ -1,0 +1,231 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars (stated per quantity, f = post-streaming populations):
+  float64 storage: max|df| / max|f| <= 1e-12, max|drho| / max|rho| <= 1e-12,
+                   max|du| <= 1e-12 absolute (lattice units);
+  float32 storage: max|df| / max|f| <= 2e-6 per step taken (float32 rounding
+                   of ~20-term sums, ~1e-7 relative per operation, growing at
+                   most linearly over a few steps), max|du| <= 1e-6 per step.
+Sizes span several tiles plus ragged tails in every axis.
+"""
+import numpy as np
+import pytest
+
+import plbm_synth as syn
+from oracle import diag as OD
+from oracle import step as S
+from oracle.lattice import LATTICES
+
+from gpu_cases import abs_max, fmt, lib_params, oracle_params, random_state, rel_max, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": (1e-12, 1e-12), "f32": (2e-6, 1e-6)}  # (relative f and rho per run, absolute u) ; f32 per step
+
+
+def _tols(storage, steps):
+    tf, tu = TOL[storage]
+    if storage == "f32":
+        return tf * max(steps, 1), tu * max(steps, 1)
+    return tf, tu
+
+
+CASES = [
+    # lattice, dims, collision, storage, walls, steps, extra
+    ("D2Q9", (37, 29), "bgk", "f64", False, 6, {}),
+    ("D2Q9", (150, 21), "mrt", "f64", True, 6, {"tau_v": 0.8, "tau_l": 1.3, "Fg": (2e-5, -1e-5)}),
+    ("D2Q9", (131, 67), "mrt", "f64", False, 5, {"kappa": 1.6}),
+    ("D2Q9", (200, 9), "bgk", "f32", True, 5, {"Fg": (1e-5, 0.0)}),
+    ("D3Q19", (37, 21, 13), "bgk", "f64", False, 4, {}),
+    ("D3Q19", (40, 18, 11), "mrt", "f64", True, 4, {"tau_v": 0.8, "tau_l": 1.2, "Fg": (1e-5, 2e-6, -3e-6)}),
+    ("D3Q19", (33, 35, 9), "mrt", "f64", False, 3, {"kappa": 0.7, "tau_v": 1.1, "tau_l": 0.9}),
+    ("D3Q19", (35, 17, 10), "mrt", "f32", False, 3, {}),
+    ("D3Q19", (32, 16, 12), "bgk", "f32", True, 3, {"Fg": (1e-5, 0.0, 0.0)}),
+]
+
+
+def _ids(c):
+    return f"{c[0]}-{'x'.join(map(str, c[1]))}-{c[2]}-{c[3]}-{'bb' if c[4] else 'per'}"
+
+
+def _run_pair(lattice, dims, collision, storage, walls, steps, extra, seed=3):
+    from paper_2504_15018_amd.lattice import Lattice
+    f0 = random_state(lattice, dims, seed)
+    op = oracle_params(lattice, collision=collision, walls=walls, **extra)
+    lp = lib_params(**{k: v for k, v in extra.items()})
+    lat = Lattice(lattice, dims, lp, collision=collision, storage=storage, walls=walls)
+    lat.write_populations(f0)
+    if storage != "f64":
+        f0 = lat.populations()  # the state as rounded into storage
+    lat.step(steps)
+    f_ref = S.run(op, f0, steps)
+    return lat, op, f_ref
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_step_parity(case):
+    require_gpu()
+    lattice, dims, collision, storage, walls, steps, extra = case
+    fmt("step_parity", case=_ids(case))
+    lat, op, f_ref = _run_pair(*case)
+    tf, tu = _tols(storage, steps)
+    f = lat.populations()
+    assert f.shape == f_ref.shape
+    assert rel_max(f, f_ref) <= tf
+    rho, u = lat.moments()
+    rho_ref, u_ref = S.moments(op, f_ref)
+    assert rel_max(rho, rho_ref) <= tf
+    assert abs_max(u, u_ref) <= tu
+    lat.close()
+
+
+@pytest.mark.parametrize("case", [c for c in CASES if c[3] == "f64"], ids=_ids)
+def test_reduction_parity(case):
+    require_gpu()
+    fmt("reduction_parity", case=_ids(case))
+    lat, op, f_ref = _run_pair(*case)
+    d = lat.reduce()
+    ref, _ = OD.reduce(op, f_ref)
+    assert d.mass == pytest.approx(ref["mass"], rel=1e-14)
+    for a in range(lat.D):
+        assert d.momentum[a] == pytest.approx(ref["momentum"][a], rel=1e-11, abs=1e-12)
+    assert d.max_u == pytest.approx(ref["max_u"], rel=1e-11, abs=1e-13)
+    assert d.flags == ref["flags"] == 0
+    assert d.time == case[5]
+    lat.close()
+
+
+@pytest.mark.parametrize("lattice,dims", [("D2Q9", (45, 31)), ("D3Q19", (34, 19, 12))])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_init_fields_is_the_equilibrium(lattice, dims, storage):
+    require_gpu()
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("init_fields", lattice=lattice, storage=storage)
+    lat_o = LATTICES[lattice]
+    co = syn.grid(dims)
+    rho0 = syn.perturb(syn.droplet(co, dims, 0.25, 7.0, R=8.0), co, dims, 5, 0.05)
+    u0 = syn.random_velocity(co, dims, 6, 0.05)
+    lat = Lattice(lattice, dims, lib_params(), storage=storage)
+    lat.init_fields(rho0, u0)
+    f = lat.populations()
+    ref = S.init_equilibrium(lat_o, rho0, u0)
+    assert rel_max(f, ref) <= (2e-16 * 8 if storage == "f64" else 1e-7)
+    lat.close()
+
+
+@pytest.mark.parametrize("lattice,dims,walls", [("D2Q9", (40, 33), True), ("D3Q19", (30, 20, 14), False)])
+def test_init_shape_matches_host_fields(lattice, dims, walls):
+    require_gpu()
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("init_shape", lattice=lattice)
+    co = syn.grid(dims)
+    R = 7.5
+    rho0 = syn.droplet(co, dims, 0.2, 7.1, R=R, W=5.0)
+    a = Lattice(lattice, dims, lib_params(), walls=walls)
+    b = Lattice(lattice, dims, lib_params(), walls=walls)
+    a.init_fields(rho0)
+    b.init_shape(N.PLBM_SHAPE_DROPLET, 7.1, 0.2, W=5.0, R=R)
+    assert rel_max(b.populations(), a.populations()) <= 1e-14
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
+def test_write_read_roundtrip(storage):
+    require_gpu()
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("roundtrip", storage=storage)
+    dims = (23, 17, 9)
+    f0 = random_state("D3Q19", dims, 11)
+    lat = Lattice("D3Q19", dims, lib_params(), storage=storage, walls=True)
+    lat.write_populations(f0)
+    f = lat.populations()
+    if storage == "f64":
+        assert np.array_equal(f, f0)
+    else:
+        # storage rounding only: float32 2^-24, shifted half 2^-11 and bfloat16 2^-8 of |f - w rho0|
+        tol = {"f32": 6e-8, "f16s": 5e-4 * 8, "bf16s": 4e-3 * 8}[storage]
+        assert rel_max(f, f0) <= tol
+        lat.write_populations(f)
+        assert np.array_equal(lat.populations(), f)  # idempotent on representable values
+    lat.close()
+
+
+def test_checkpoint_restart_is_bitwise():
+    require_gpu()
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("checkpoint")
+    dims = (41, 22, 10)
+    f0 = random_state("D3Q19", dims, 21)
+    a = Lattice("D3Q19", dims, lib_params(tau_v=0.9, tau_l=1.1), collision="mrt")
+    a.write_populations(f0)
+    a.step(7)
+    ck = a.populations()
+    a.step(5)
+    b = Lattice("D3Q19", dims, lib_params(tau_v=0.9, tau_l=1.1), collision="mrt")
+    b.write_populations(ck)
+    b.step(5)
+    assert np.array_equal(a.populations(), b.populations())
+    a.close()
+    b.close()
+
+
+def test_rerun_is_bitwise_deterministic():
+    require_gpu()
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("determinism")
+    dims = (70, 37, 19)
+    f0 = random_state("D3Q19", dims, 31)
+    outs = []
+    for _ in range(2):
+        lat = Lattice("D3Q19", dims, lib_params(), collision="mrt", storage="f32")
+        lat.write_populations(f0)
+        lat.step(20)
+        outs.append((lat.populations(), lat.reduce().mass))
+        lat.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+
+
+def test_planar_c1_lateral_invariance_and_oracle():
+    """256 x 4 periodic slab (PR T/Tc = 0.8): every column bitwise equal and equal to the 256 x 1 oracle."""
+    require_gpu()
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("c1_lateral")
+    op = oracle_params("D2Q9")
+    rv, rl = op.rho_v, op.rho_l
+    dims = (256, 4)
+    co = syn.grid(dims)
+    rho0 = syn.slab(co, dims, rv, rl, W=5.0, axis=0)
+    lat = Lattice("D2Q9", dims, lib_params())
+    lat.init_fields(rho0)
+    steps = 200
+    lat.step(steps)
+    f = lat.populations()
+    for y in range(1, 4):
+        assert np.array_equal(f[:, y, :], f[:, 0, :])
+    co1 = syn.grid((256, 1))
+    ref = S.run(op, S.init_equilibrium(op.lat, syn.slab(co1, (256, 1), rv, rl, W=5.0, axis=0)), steps)
+    assert rel_max(f[:, :1, :], ref) <= 1e-12
+    lat.close()
+
+
+def test_graph_replay_matches_single_launches():
+    require_gpu()
+    import os
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("graph_vs_launch")
+    dims = (64, 40, 24)
+    f0 = random_state("D3Q19", dims, 41)
+    a = Lattice("D3Q19", dims, lib_params(), collision="mrt", storage="f32")
+    a.write_populations(f0)
+    a.step(3)
+    a.step(16)  # graph path (odd start)
+    b = Lattice("D3Q19", dims, lib_params(), collision="mrt", storage="f32")
+    b.write_populations(f0)
+    for _ in range(19):
+        b.step(1)  # single launches
+    assert a.time == b.time == 19
+    assert np.array_equal(a.populations(), b.populations())
+    a.close()
+    b.close()
