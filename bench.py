@@ -72,13 +72,37 @@ print(json.dumps({"mlups": rho.size * n / dt / 1e6, "steps": n, "seconds": dt, "
                       f"in {out['seconds']:.1f} s, single thread"}
 
 
+def copy_probe(torch, nbytes=2 << 30, reps=20):
+    """Plain device-to-device copy of nbytes: the measured HBM reference for the roofline."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3 / reps
+    print(json.dumps({"copy_bytes": nbytes, "copy_ms": round(dt * 1e3, 4),
+                      "copy_GBps_read_plus_write": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--collision", default="mrt", choices=["mrt", "bgk"])
+    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16s", "bf16s"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time a plain device-to-device copy of 2 GiB (HBM reference for the roofline)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the lattice update is not sharded across GPUs here); "
@@ -89,16 +113,20 @@ def main():
     from paper_2504_15018_amd import native as N
     from paper_2504_15018_amd.lattice import Lattice
 
+    if args.copy_probe:
+        copy_probe(torch)
+        return
     N.load()
     n = args.size
     dims = (n, n, n)
     prm = N.plbm_params_pr_lattice(0.8, 0.326, 2.0, 1.0, 1.0, 1.0)
     log(f"[bench] coexistence rho_v={prm.rho_v:.6f} rho_l={prm.rho_l:.6f}")
-    lat = Lattice("D3Q19", dims, prm, collision="mrt", storage="f32")
+    lat = Lattice("D3Q19", dims, prm, collision=args.collision, storage=args.storage)
     R = 48.0 * n / 256.0
     lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=5.0, R=R, centre=[n / 2.0] * 3)
     stream = lat.stream
-    log(f"[bench] lattice {dims} D3Q19 MRT f32, {lat.nbytes / 2**30:.2f} GiB; warmup {args.warmup}")
+    log(f"[bench] lattice {dims} D3Q19 {args.collision} {args.storage}, {lat.nbytes / 2**30:.2f} GiB; "
+        f"warmup {args.warmup}")
     lat.step(args.warmup)
     d0 = lat.reduce()
     torch.cuda.synchronize()
@@ -130,7 +158,8 @@ def main():
     nodes = lat.N
     ms_per_step = wall * 1e3 / K
     mlups = nodes * K / wall / 1e6
-    bytes_per_launch = 2 * 19 * 4 * nodes
+    S = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[args.storage]
+    bytes_per_launch = 2 * 19 * S * nodes
     achieved = bytes_per_launch / avg_kernel_s / 1e9
     dfin = lat.reduce()
     log(f"[bench] {K} steps in {wall:.3f} s; step kernel avg {avg_kernel_s * 1e3:.4f} ms; "
@@ -151,12 +180,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if args.storage == "f64" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"D3Q19 static droplet {n}^3 periodic, f32 populations, MRT + Guo forcing, "
-                               f"Peng-Robinson T/Tc=0.8, radius {R:g}, tanh width 5; reduction every "
-                               f"{REDUCE_EVERY} steps",
-                   "lattice": "D3Q19", "nodes": nodes, "storage": "f32", "collision": "mrt",
+        "config": {"workload": f"D3Q19 static droplet {n}^3 periodic, {args.storage} populations, "
+                               f"{args.collision.upper()} + Guo forcing, Peng-Robinson T/Tc=0.8, radius {R:g}, "
+                               f"tanh width 5; reduction every {REDUCE_EVERY} steps",
+                   "lattice": "D3Q19", "nodes": nodes, "storage": args.storage, "collision": args.collision,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},

@@ -52,25 +52,33 @@ def _compile(src, extra):
     return obj
 
 
-def build(jobs=None, verbose=False):
+def build(jobs=None, verbose=False, out=None, defines=()):
+    """Compile every source and link libplbm.so (or `out`)."""
+    global BUILD
+    if out is not None:
+        BUILD = os.path.join(os.path.dirname(os.path.abspath(out)), "_build")
     os.makedirs(BUILD, exist_ok=True)
+    extra_defs = [f"-D{d}" for d in defines]
     jobs = jobs or min(6, os.cpu_count() or 2)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda kv: _compile(*kv), SOURCES.items()))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda kv: _compile(kv[0], kv[1] + extra_defs), SOURCES.items()))
+    lib = os.path.abspath(out) if out is not None else LIB
+    tmp = lib + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--out", default=None, help="library path (default: in-tree libplbm.so)")
+    ap.add_argument("-D", dest="defines", action="append", default=[], help="extra preprocessor definition")
     a = ap.parse_args()
-    build(a.jobs, verbose=True)
+    build(a.jobs, verbose=True, out=a.out, defines=a.defines)
     sys.exit(0)

@@ -49,6 +49,8 @@ struct Layout {
   int Q, D;
   int nxk, nyk, nzk;  // kernel axes
   int tx, ty, cz, tiles_x, tiles_y, tiles_z, ntiles;
+  int nxb;         // 128-byte x blocks per row of stored populations
+  uint64_t zblock; // bytes of one z plane of stored populations
   int64_t N;
   uint64_t popA, popB, aux, uprev, red, kp, total;
 };
@@ -97,11 +99,15 @@ int make_layout(const plbm_lattice_desc* d, Layout* L) {
   if (nt > 0x3fffffff) return set_error(PLBM_E_INVALID, "too many tiles");
   L->ntiles = (int)nt;
   const uint64_t S = storage_bytes(d->storage);
+  const int XB = (int)(128 / S);
+  L->nxb = (L->nxk + XB - 1) / XB;
+  L->zblock = (uint64_t)L->nyk * L->nxb * L->Q * 128;
+  if (L->zblock >= (1ull << 31)) return set_error(PLBM_E_UNSUPPORTED, "one z plane of populations exceeds 2 GiB");
   uint64_t off = 0;
   L->popA = off;
-  off = align_up(off + (uint64_t)L->Q * L->N * S);
+  off = align_up(off + L->zblock * L->nzk);
   L->popB = off;
-  off = align_up(off + (uint64_t)L->Q * L->N * S);
+  off = align_up(off + L->zblock * L->nzk);
   L->aux = off;
   off = align_up(off + 4ull * L->N * 8);
   L->uprev = off;
@@ -234,6 +240,8 @@ void fill_kparams(plbm_lattice* L) {
                      ? (L->desc.rho0_shift > 0 ? L->desc.rho0_shift : p.rho_l)
                      : 0.0;
   k.parity = 0;
+  k.nxb = y.nxb;
+  k.zblock = (int64_t)y.zblock;
 }
 
 int check_lat(plbm_lattice* L) { return L ? PLBM_OK : set_error(PLBM_E_INVALID, "null lattice"); }

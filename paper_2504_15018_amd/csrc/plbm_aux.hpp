@@ -6,23 +6,31 @@
 
 namespace plbm {
 
-// Storage slot that holds f_i(x) of the post-streaming state: A_i(x - c_i),
-// or A_opp(i)(x) when x - c_i lies beyond a half-way bounce-back wall.
-template <class L>
-__device__ __forceinline__ void storage_slot(const KParams& p, int i, int x, int y, int z, int* dir, int64_t* idx) {
+// Storage index (in elements of T) of f_i(x) of the post-streaming state.
+// Populations are kept post-collision: f_i(x) lives at A_i(x - c_i), or at
+// A_opp(i)(x) when x - c_i lies beyond a half-way bounce-back wall.
+template <class L, class T>
+__device__ __forceinline__ int64_t storage_index(const KParams& p, int i, int x, int y, int z) {
+  constexpr int XB = Lines<T>::XB;
   const int nx = p.nx, ny = p.ny, nz = p.nz;
-  int sz = z - L::cz[i];
+  int sz = z - L::cz[i], sx = x - L::cx[i], sy = y - L::cy[i], q = i;
   if (p.bb_z && (sz < 0 || sz >= nz)) {
-    *dir = L::opp[i];
-    *idx = ((int64_t)z * ny + y) * nx + x;
-    return;
+    sx = x;
+    sy = y;
+    sz = z;
+    q = L::opp[i];
   }
-  int sx = x - L::cx[i], sy = y - L::cy[i];
   sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
   sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
   sz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
-  *dir = i;
-  *idx = ((int64_t)sz * ny + sy) * nx + sx;
+  return ((((int64_t)sz * ny + sy) * p.nxb + sx / XB) * L::Q + q) * XB + sx % XB;
+}
+
+// Direction whose storage slot holds f_i(x) (differs from i only at walls).
+template <class L>
+__device__ __forceinline__ int storage_dir(const KParams& p, int i, int z) {
+  const int sz = z - L::cz[i];
+  return (p.bb_z && (sz < 0 || sz >= p.nz)) ? L::opp[i] : i;
 }
 
 // Second-order equilibrium of eq. (Single_Phase_EDF), float64.
@@ -43,10 +51,8 @@ __device__ __forceinline__ void write_equilibrium(const KParams& p, int par, int
   typename St::T* A = reinterpret_cast<typename St::T*>(p.pop[par]);
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
-    int dir;
-    int64_t idx;
-    storage_slot<L>(p, i, x, y, z, &dir, &idx);
-    A[(size_t)dir * (size_t)p.N + idx] = St::enc64(feq64<L>(i, rho, u), L::w[dir] * p.rho0_shift);
+    const int dir = storage_dir<L>(p, i, z);
+    A[storage_index<L, typename St::T>(p, i, x, y, z)] = St::enc64(feq64<L>(i, rho, u), L::w[dir] * p.rho0_shift);
   }
 }
 
@@ -116,10 +122,8 @@ __global__ __launch_bounds__(256) void k_read_pop(const KParams* __restrict__ P,
   for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < p.N; n += (int64_t)gridDim.x * blockDim.x) {
     int x, y, z;
     node_xyz(p, n, &x, &y, &z);
-    int dir;
-    int64_t idx;
-    storage_slot<L>(p, dirq, x, y, z, &dir, &idx);
-    out[n] = St::dec64(A[(size_t)dir * (size_t)p.N + idx], L::w[dir] * p.rho0_shift);
+    const int dir = storage_dir<L>(p, dirq, z);
+    out[n] = St::dec64(A[storage_index<L, typename St::T>(p, dirq, x, y, z)], L::w[dir] * p.rho0_shift);
   }
 }
 
@@ -132,10 +136,8 @@ __global__ __launch_bounds__(256) void k_write_pop(const KParams* __restrict__ P
   for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < p.N; n += (int64_t)gridDim.x * blockDim.x) {
     int x, y, z;
     node_xyz(p, n, &x, &y, &z);
-    int dir;
-    int64_t idx;
-    storage_slot<L>(p, dirq, x, y, z, &dir, &idx);
-    A[(size_t)dir * (size_t)p.N + idx] = St::enc64(in[n], L::w[dir] * p.rho0_shift);
+    const int dir = storage_dir<L>(p, dirq, z);
+    A[storage_index<L, typename St::T>(p, dirq, x, y, z)] = St::enc64(in[n], L::w[dir] * p.rho0_shift);
   }
 }
 

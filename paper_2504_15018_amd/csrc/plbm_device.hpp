@@ -27,6 +27,10 @@ struct D2Q9L {
                                   1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
   // physical component a (0: x, 1: y of the 2-D lattice)
   static constexpr int c(int i, int a) { return a == 0 ? cx[i] : cz[i]; }
+  // opposite pairs (pa[p], pb[p]) with c_pb = -c_pa
+  static constexpr int P = 4;
+  static constexpr int pa[4] = {1, 2, 5, 6};
+  static constexpr int pb[4] = {3, 4, 7, 8};
 };
 
 struct D3Q19L {
@@ -40,6 +44,9 @@ struct D3Q19L {
                                    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
                                    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
   static constexpr int c(int i, int a) { return a == 0 ? cx[i] : (a == 1 ? cy[i] : cz[i]); }
+  static constexpr int P = 9;
+  static constexpr int pa[9] = {1, 3, 5, 7, 9, 11, 13, 15, 17};
+  static constexpr int pb[9] = {2, 4, 6, 8, 10, 12, 14, 16, 18};
 };
 
 // MRT extension: the non-hydrodynamic moments whose rate differs from the
@@ -87,12 +94,23 @@ struct MrtCorr<D3Q19L> {
   }
 };
 
+// 1 / |P_k|^2 as a compile-time table (folded into the unrolled kernels).
 template <class L>
-constexpr double mrt_norm(int k) {
-  double s = 0;
-  for (int i = 0; i < L::Q; ++i) s += MrtCorr<L>::P(k, i) * MrtCorr<L>::P(k, i);
-  return s;
-}
+struct MrtInvNorm {
+  struct Tab {
+    double v[MrtCorr<L>::K];
+  };
+  static constexpr Tab make() {
+    Tab t{};
+    for (int k = 0; k < MrtCorr<L>::K; ++k) {
+      double s = 0;
+      for (int i = 0; i < L::Q; ++i) s += MrtCorr<L>::P(k, i) * MrtCorr<L>::P(k, i);
+      t.v[k] = 1.0 / s;
+    }
+    return t;
+  }
+  static constexpr Tab tab = make();
+};
 
 // ---------------------------------------------------------------------------
 // Storage codecs.  Shifted storage keeps f_i - w_i rho0 (one global rho0) so
@@ -174,25 +192,75 @@ struct KParams {
   double rates[4];                 // s_e, s_eps, s_q, s_m
   double rho0_shift;
   int32_t parity;  // batch slots: A-B phase offset of this lattice
-  int32_t pad0;
+  int32_t nxb;     // x blocks of one 128-byte line per row (storage layout)
+  int64_t zblock;  // bytes of one z plane of stored populations
 };
 
+// Stored population layout: A[z][y][x / XB][q][x % XB] with XB = 128 / sizeof(T),
+// so that the innermost unit is one 128-byte line of one direction.  All
+// directions of a node sit at a common offset plus q * 128 bytes.
+template <class T>
+struct Lines {
+  static constexpr int XB = 128 / (int)sizeof(T);
+};
+
+// Equation-of-state constants held in scalar registers by the kernels.
+struct EosK {
+  int32_t kind;
+  double K, c2, sv, rl, rl2;  // paper EOS: p = K [2 r^3 + c2 r^2 + sv sqrt(r) (-3 r^2 + 2 rl r + rl2)]
+  double RT, b, aa;           // Peng-Robinson: p = r RT / (1 - b r) - aa r^2 / (1 + 2 b r - b^2 r^2)
+};
+
+__device__ __forceinline__ EosK load_eos(const KParams* __restrict__ kp) {
+  EosK e;
+  e.kind = kp->eos;
+  e.K = kp->K;
+  e.c2 = kp->e_rv - 2.0 * kp->e_rl;
+  e.sv = kp->e_sqrt_rv;
+  e.rl = kp->e_rl;
+  e.rl2 = kp->e_rl * kp->e_rl;
+  e.RT = kp->pr_RT;
+  e.b = kp->pr_b;
+  e.aa = kp->pr_aalpha;
+  return e;
+}
+
 // psi(rho) of eq. (Interaction_Potential), G = -1, lattice units, float64.
-// Returns the clamped value; *neg is set when the radicand was negative.
-__device__ __forceinline__ double psi_of_rho(const KParams& p, double rho, bool* neg) {
+// The two Peng-Robinson fractions share one division.  Returns the clamped
+// value; *neg is set when the radicand was negative.
+__device__ __forceinline__ double psi_radicand(const EosK& e, double rho) {
   double pe;
-  if (p.eos == EOS_PAPER) {
-    double r2 = rho * rho;
-    double s = sqrt(rho);
-    pe = p.K * (2.0 * r2 * rho + (p.e_rv - 2.0 * p.e_rl) * r2 +
-                p.e_sqrt_rv * s * (-3.0 * r2 + 2.0 * p.e_rl * rho + p.e_rl * p.e_rl));
+  const double r2 = rho * rho;
+  if (e.kind == EOS_PAPER) {
+    const double s = sqrt(rho);
+    pe = e.K * (2.0 * r2 * rho + e.c2 * r2 + e.sv * s * (-3.0 * r2 + 2.0 * e.rl * rho + e.rl2));
   } else {
-    double b = p.pr_b;
-    pe = rho * p.pr_RT / (1.0 - b * rho) - p.pr_aalpha * rho * rho / (1.0 + 2.0 * b * rho - b * b * rho * rho);
+    const double d1 = 1.0 - e.b * rho;
+    const double d2 = 1.0 + 2.0 * e.b * rho - e.b * e.b * r2;
+    pe = (rho * e.RT * d2 - e.aa * r2 * d1) / (d1 * d2);
   }
-  double rad = 2.0 * (rho / 3.0 - pe);
+  return 2.0 * (rho * (1.0 / 3.0) - pe);
+}
+
+// psi in the arithmetic type C: the radicand (where p_EOS and rho/3 cancel)
+// is always float64; a float32 result takes the square root in float32.
+template <class C>
+__device__ __forceinline__ C psi_eval(const EosK& e, double rho, bool* neg);
+template <>
+__device__ __forceinline__ double psi_eval<double>(const EosK& e, double rho, bool* neg) {
+  const double rad = psi_radicand(e, rho);
   *neg = !(rad >= 0.0);
   return sqrt(rad > 0.0 ? rad : 0.0);
 }
+template <>
+__device__ __forceinline__ float psi_eval<float>(const EosK& e, double rho, bool* neg) {
+  const double rad = psi_radicand(e, rho);
+  *neg = !(rad >= 0.0);
+  return sqrtf(rad > 0.0 ? (float)rad : 0.0f);
+}
+
+// Reciprocal: IEEE division in float64; the hardware reciprocal (1 ulp) in float32.
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 }  // namespace plbm

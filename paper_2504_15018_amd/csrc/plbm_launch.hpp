@@ -13,13 +13,13 @@ namespace plbm {
 struct WorkItem;
 struct ShapeK;
 
-// Compile-time tile shapes: D3Q19 32 x 16 nodes per workgroup of 256 threads
-// (2 nodes per thread per plane); D2Q9 rows of 128 nodes per 128 threads.
+// Compile-time tile shapes: D3Q19 32 x 8 nodes per workgroup of 256 threads
+// (one node per thread per plane); D2Q9 rows of 128 nodes per 128 threads.
 template <class L>
 struct TileShape;
 template <>
 struct TileShape<D3Q19L> {
-  static constexpr int TX = 32, TY = 16, NT = 256;
+  static constexpr int TX = 32, TY = 8, NT = 256;
 };
 template <>
 struct TileShape<D2Q9L> {

@@ -18,6 +18,10 @@
 
 namespace plbm {
 
+#ifndef PLBM_MIN_WAVES
+#define PLBM_MIN_WAVES 2  // waves per SIMD the register allocation must allow
+#endif
+
 enum : int { COLL_BGK = 0, COLL_MRT = 1 };
 enum : int { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_REDUCE = 2 };
 
@@ -52,19 +56,193 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return (b & 7) * (nfull >> 3) + (b >> 3);
 }
 
+// Loads and stores through a scalar (wave-uniform) base pointer in the global
+// address space plus a 32-bit byte offset: global_load/store with an SGPR
+// base.  The library keeps every per-direction array below 4 GiB.
+template <class T>
+__device__ __forceinline__ T gld(const void* base, uint32_t byte_off) {
+  typedef const __attribute__((address_space(1))) char gchar;
+  typedef const __attribute__((address_space(1))) T gT;
+  return *(gT*)((gchar*)base + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void gst(void* base, uint32_t byte_off, T v) {
+  typedef __attribute__((address_space(1))) char gchar;
+  typedef __attribute__((address_space(1))) T gT;
+  *(gT*)((gchar*)base + byte_off) = v;
+}
+
+// psi stencil and interaction force at one node (Sec. II):
+//   M1_a = 3 sum_i w_i psi_i c_ia,  M2_ab = 9 sum_i w_i psi_i c_ia c_ib - 3 delta_ab sum_i w_i psi_i,
+//   F = cA psi M1 + cB (M1.M2) + cC M1 tr(M2) + F_g,
+// summed over opposite pairs: psi_a + psi_b carries the even moments,
+// psi_a - psi_b the odd ones.
+template <class L, class C, int W2>
+__device__ __forceinline__ void stencil_force(const C* s_m, const C* s_0, const C* s_p, int il, C cA, C cB, C cC,
+                                              const C* Fg, C* F) {
+  constexpr int D = L::D;
+  auto psi_at = [&](int i) {
+    const int cz = L::cz[i];
+    const C* sl = cz > 0 ? s_p : (cz < 0 ? s_m : s_0);
+    return sl[il + L::cy[i] * W2 + L::cx[i]];
+  };
+  const C psi_c = s_0[il];
+  C S0 = (C)L::w[0] * psi_c, S1[D], S2[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    S1[a] = 0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) S2[a][b] = 0;
+  }
+#pragma unroll
+  for (int p = 0; p < L::P; ++p) {
+    const int ia = L::pa[p];
+    const C pa = psi_at(ia), pb = psi_at(L::pb[p]);
+    const C sum = pa + pb, dif = pa - pb;
+    const C w = (C)L::w[ia];
+    S0 += w * sum;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int ca = L::c(ia, a);
+      if (ca != 0) S1[a] += (C)(ca)*w * dif;
+#pragma unroll
+      for (int b = a; b < D; ++b) {
+        const int cc = ca * L::c(ia, b);
+        if (cc != 0) S2[a][b] += (C)(cc)*w * sum;
+      }
+    }
+  }
+  C M1[D], M2[D][D], tr = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    M1[a] = (C)3 * S1[a];
+#pragma unroll
+    for (int b = a; b < D; ++b) {
+      M2[a][b] = (C)9 * S2[a][b] - (a == b ? (C)3 * S0 : (C)0);
+      M2[b][a] = M2[a][b];
+    }
+    tr += M2[a][a];
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    C m1m2 = 0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) m1m2 += M1[b] * M2[a][b];
+    F[a] = cA * psi_c * M1[a] + cB * m1m2 + cC * M1[a] * tr + Fg[a];
+  }
+}
+
+// BGK collision with Guo forcing (eqs. LBE, Single_Phase_EDF,
+// Guo_Forcing_Scheme), dt = 1:  f* = (1 - omega) f + omega f_eq + (1 - omega/2) Fhat,
+// written per opposite pair (a, b = opp a) through even and odd parts:
+//   f_eq = E +- O,  E = w rho (1 - 1.5 u.u + 4.5 (c.u)^2),  O = 3 w rho (c.u)
+//   Fhat = hE +- hO, hE = w (9 (c.u)(c.F) - 3 u.F),      hO = 3 w (c.F).
+// MRT adds  - sum_k (s_k - omega) P_k(c_i) (sum_j P_k(c_j) v_j) / |P_k|^2 with
+// v = f - f_eq + Fhat/2 over the non-hydrodynamic moments of MrtCorr<L>; the
+// moment sums read v_a + v_b (even P_k) or v_a - v_b (odd P_k).
+// dp[p] = f_a - f_b is shared with the momentum sum.
+template <class L, class C, int COLL>
+__device__ __forceinline__ void collide(const C* f, const C* dp, C rho, const C* u, const C* F, C omega,
+                                        const C* rate, C* fs) {
+  constexpr int D = L::D;
+  using MC = MrtCorr<L>;
+  constexpr int K = (COLL == COLL_MRT) ? MC::K : 1;
+  C usq = 0, uF = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    usq += u[a] * u[a];
+    uF += u[a] * F[a];
+  }
+  const C A = (C)1 - (C)1.5 * usq;
+  const C om1 = (C)1 - omega;
+  const C omh = (C)1 - (C)0.5 * omega;
+  const C w0 = (C)L::w[0];
+  const C E0 = w0 * rho * A;
+  const C h0 = -(C)3 * w0 * uF;
+  C B0 = omega * E0 + omh * h0;
+  C BE[L::P], BO[L::P];
+  C mk[K];
+  if (COLL == COLL_MRT) {
+    const C v0 = f[0] - E0 + (C)0.5 * h0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) mk[k] = (MC::P(k, 0) != 0.0) ? (C)MC::P(k, 0) * v0 : (C)0;
+  }
+#pragma unroll
+  for (int p = 0; p < L::P; ++p) {
+    const int ia = L::pa[p], ib = L::pb[p];
+    C cu = 0, cF = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (L::c(ia, a) > 0) {
+        cu += u[a];
+        cF += F[a];
+      }
+      if (L::c(ia, a) < 0) {
+        cu -= u[a];
+        cF -= F[a];
+      }
+    }
+    const C w = (C)L::w[ia];
+    const C E = (w * rho) * (A + (C)4.5 * cu * cu);
+    const C O = ((C)3 * w * rho) * cu;
+    const C hE = (C)9 * w * (cu * cF) - (C)3 * w * uF;
+    const C hO = ((C)3 * w) * cF;
+    const C be = omega * E + omh * hE;
+    const C bo = omega * O + omh * hO;
+    if (COLL == COLL_MRT) {
+      BE[p] = be;
+      BO[p] = bo;
+      const C vs = (f[ia] + f[ib]) - (C)2 * E + hE;  // v_a + v_b
+      const C vd = dp[p] - (C)2 * O + hO;             // v_a - v_b
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double ca = MC::P(k, ia), cb = MC::P(k, ib);
+        if (ca != 0.0) mk[k] += (C)ca * (ca == cb ? vs : vd);
+      }
+    } else {
+      fs[ia] = om1 * f[ia] + (be + bo);
+      fs[ib] = om1 * f[ib] + (be - bo);
+    }
+  }
+  if (COLL == COLL_MRT) {
+    C coef[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) coef[k] = (rate[MC::rate_class[k]] - omega) * ((C)MrtInvNorm<L>::tab.v[k] * mk[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (MC::P(k, 0) != 0.0) B0 -= (C)MC::P(k, 0) * coef[k];
+#pragma unroll
+    for (int p = 0; p < L::P; ++p) {
+      C be = BE[p], bo = BO[p];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double ca = MC::P(k, L::pa[p]), cb = MC::P(k, L::pb[p]);
+        if (ca == cb) {
+          if (ca != 0.0) be -= (C)ca * coef[k];
+        } else {
+          bo -= (C)ca * coef[k];
+        }
+      }
+      fs[L::pa[p]] = om1 * f[L::pa[p]] + (be + bo);
+      fs[L::pb[p]] = om1 * f[L::pb[p]] + (be - bo);
+    }
+  }
+  fs[0] = om1 * f[0] + B0;
+}
+
 template <class L, class St, int COLL, int MODE, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT) void k_step(const KParams* __restrict__ P, const WorkItem* __restrict__ work,
+__global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __restrict__ P, const WorkItem* __restrict__ work,
                                              int32_t nwork, int32_t phase, double* __restrict__ out_rho,
                                              double* __restrict__ out_u) {
   using T = typename St::T;
   using C = typename St::C;
   constexpr int Q = L::Q, D = L::D, HY = L::HY;
-  constexpr int S = (TX * TY) / NT;  // interior nodes per thread per plane
-  static_assert(S * NT == TX * TY, "tile must be a multiple of the block");
+  static_assert(TX * TY == NT, "one node per thread per plane");
   constexpr int W2 = TX + 2;
   constexpr int PL = W2 * (TY + 2 * HY);  // LDS plane (tile + halo)
   constexpr int H = PL - TX * TY;         // halo nodes per plane
-  constexpr int HPT = (H + NT - 1) / NT;  // halo nodes per thread (upper bound)
+  static_assert(H <= NT, "halo fits one node per thread");
+  constexpr uint32_t TS = sizeof(T);
 
   __shared__ C lds_psi[4 * PL];
   __shared__ RedRec red_lds[(MODE == MODE_REDUCE) ? NT : 1];
@@ -76,52 +254,65 @@ __global__ __launch_bounds__(NT) void k_step(const KParams* __restrict__ P, cons
     slot = work[wid].slot;
     tile = work[wid].tile;
   }
-  const KParams p = P[slot];
-  if (tile >= p.ntiles) return;
+  const KParams* __restrict__ kp = P + slot;
+  if (tile >= kp->ntiles) return;
 
-  const int nx = p.nx, ny = p.ny, nz = p.nz;
-  const int64_t N = p.N;
-  const int txi = tile % p.tiles_x;
-  const int tyi = (tile / p.tiles_x) % p.tiles_y;
-  const int tzi = tile / (p.tiles_x * p.tiles_y);
-  const int x0 = txi * TX, y0 = tyi * TY, z0 = tzi * p.cz;
-  const int z1 = min(z0 + p.cz, nz);
-  const int par = (phase + p.parity) & 1;
-  const T* __restrict__ src = reinterpret_cast<const T*>(p.pop[par]);
-  T* __restrict__ dst = reinterpret_cast<T*>(p.pop[par ^ 1]);
+  const int nx = kp->nx, ny = kp->ny, nz = kp->nz;
+  const uint32_t N = (uint32_t)kp->N;
+  constexpr int XB = Lines<T>::XB;
+  const int nxb = kp->nxb;
+  const uint64_t zblock = (uint64_t)kp->zblock;  // bytes of one z plane of populations
+  const int tiles_x = kp->tiles_x, tiles_y = kp->tiles_y, czc = kp->cz;
+  const int txi = tile % tiles_x;
+  const int tyi = (tile / tiles_x) % tiles_y;
+  const int tzi = tile / (tiles_x * tiles_y);
+  const int x0 = txi * TX, y0 = tyi * TY, z0 = tzi * czc;
+  const int z1 = min(z0 + czc, nz);
+  const int par = (phase + kp->parity) & 1;
+  char* const pop0 = reinterpret_cast<char*>(kp->pop[0]);
+  char* const pop1 = reinterpret_cast<char*>(kp->pop[1]);
+  const char* const src = par ? pop1 : pop0;
+  char* const dst = par ? pop0 : pop1;
   const int plane = nx * ny;
-  const bool bbz = p.bb_z != 0;
+  const bool bbz = kp->bb_z != 0;
+  const EosK eos = load_eos(kp);
+  const double rho0_shift = kp->rho0_shift;
 
   C shift[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) shift[i] = (C)(L::w[i] * p.rho0_shift);
+  for (int i = 0; i < Q; ++i) shift[i] = (C)(L::w[i] * rho0_shift);
 
-  // ---- per-thread node coordinates (fixed for the whole z march) ----
+  // ---- node offsets of this thread, fixed for the whole z march ----
+  // oxy[(cx+1) + 3 (cy+1)] = byte offset, within a z plane of stored
+  // populations, of direction 0 of the pull source (x - cx, y - cy);
+  // direction q adds q * 128 bytes.
   const int t = threadIdx.x;
-  int ix[S], ixm[S], ixp[S], iyo[S], iyom[S], iyop[S], ilds[S];
-  bool ivalid[S];
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    int flat = t + s * NT;
-    int lx = flat % TX, ly = flat / TX;
+  auto node_off = [&](int x, int y) -> uint32_t {
+    return (uint32_t)((((y * nxb + x / XB) * Q) * XB + x % XB) * (int)TS);
+  };
+  uint32_t ioxy[9], hoxy[9];
+  int ilds, hlds, own;
+  bool ivalid, hact;
+  {
+    const int lx = t % TX, ly = t / TX;
     int gx = x0 + lx, gy = y0 + ly;
-    ivalid[s] = (gx < nx) && (gy < ny);
-    gx = gx % nx;  // ragged tile: wrapped duplicate, never stored
-    gy = gy % ny;
-    ix[s] = gx;
-    ixm[s] = gx == 0 ? nx - 1 : gx - 1;
-    ixp[s] = gx == nx - 1 ? 0 : gx + 1;
-    iyo[s] = gy * nx;
-    iyom[s] = (gy == 0 ? ny - 1 : gy - 1) * nx;
-    iyop[s] = (gy == ny - 1 ? 0 : gy + 1) * nx;
-    ilds[s] = (ly + HY) * W2 + (lx + 1);
-  }
-  int hx[HPT], hxm[HPT], hxp[HPT], hyo[HPT], hyom[HPT], hyop[HPT], hlds[HPT];
-  bool hact[HPT];
+    ivalid = (gx < nx) && (gy < ny);
+    gx = gx < nx ? gx : gx % nx;  // ragged tile: a wrapped duplicate, never stored
+    gy = gy < ny ? gy : gy % ny;
+    const int xm = gx == 0 ? nx - 1 : gx - 1, xp = gx == nx - 1 ? 0 : gx + 1;
+    const int ym = gy == 0 ? ny - 1 : gy - 1, yp = gy == ny - 1 ? 0 : gy + 1;
 #pragma unroll
-  for (int k = 0; k < HPT; ++k) {
-    int h = t + k * NT;
-    hact[k] = h < H;
+    for (int cy = -1; cy <= 1; ++cy)
+#pragma unroll
+      for (int cx = -1; cx <= 1; ++cx)
+        ioxy[(cx + 1) + 3 * (cy + 1)] =
+            node_off(cx > 0 ? xm : (cx < 0 ? xp : gx), cy > 0 ? ym : (cy < 0 ? yp : gy));
+    ilds = (ly + HY) * W2 + (lx + 1);
+    own = gy * nx + gx;
+  }
+  {
+    const int h = t;
+    hact = h < H;
     int lx, ly;
     if (HY) {
       if (h < W2) {
@@ -131,7 +322,7 @@ __global__ __launch_bounds__(NT) void k_step(const KParams* __restrict__ P, cons
         lx = h - W2 - 1;
         ly = TY;
       } else {
-        int r = h - 2 * W2;
+        const int r = h - 2 * W2;
         lx = (r & 1) ? TX : -1;
         ly = r >> 1;
       }
@@ -139,37 +330,49 @@ __global__ __launch_bounds__(NT) void k_step(const KParams* __restrict__ P, cons
       lx = (h & 1) ? TX : -1;
       ly = 0;
     }
-    if (!hact[k]) {
+    if (!hact) {
       lx = 0;
       ly = 0;
     }
-    int gx = ((x0 + lx) % nx + nx) % nx;  // periodic in x and y
-    int gy = ((y0 + ly) % ny + ny) % ny;
-    hx[k] = gx;
-    hxm[k] = gx == 0 ? nx - 1 : gx - 1;
-    hxp[k] = gx == nx - 1 ? 0 : gx + 1;
-    hyo[k] = gy * nx;
-    hyom[k] = (gy == 0 ? ny - 1 : gy - 1) * nx;
-    hyop[k] = (gy == ny - 1 ? 0 : gy + 1) * nx;
-    hlds[k] = (ly + HY) * W2 + (lx + 1);
+    const int gx = ((x0 + lx) % nx + nx) % nx;  // periodic in x and y
+    const int gy = ((y0 + ly) % ny + ny) % ny;
+    const int xm = gx == 0 ? nx - 1 : gx - 1, xp = gx == nx - 1 ? 0 : gx + 1;
+    const int ym = gy == 0 ? ny - 1 : gy - 1, yp = gy == ny - 1 ? 0 : gy + 1;
+#pragma unroll
+    for (int cy = -1; cy <= 1; ++cy)
+#pragma unroll
+      for (int cx = -1; cx <= 1; ++cx)
+        hoxy[(cx + 1) + 3 * (cy + 1)] =
+            node_off(cx > 0 ? xm : (cx < 0 ? xp : gx), cy > 0 ? ym : (cy < 0 ? yp : gy));
+    hlds = (ly + HY) * W2 + (lx + 1);
   }
 
-  // Pull the populations of one node of plane pz (pz already in [0, nz)).
-  auto pull = [&](int x, int xm, int xp, int yo, int yom, int yop, int zo, int zom, int zop, bool lo, bool hi,
-                  C* f) {
+  // logical plane zl (may be -1 or nz) -> stored plane
+  auto wrapz = [&](int zl) {
+    if (zl < 0) return bbz ? 0 : zl + nz;
+    if (zl >= nz) return bbz ? nz - 1 : zl - nz;
+    return zl;
+  };
+
+  // Pull the Q populations of one node of stored plane pz; bm, b0, bp are
+  // the population blocks of the planes pz-1, pz, pz+1.
+  auto pull = [&](const uint32_t* oxy, const char* bm, const char* b0, const char* bp, bool lo, bool hi, C* f) {
+    if (!(lo || hi)) {  // wave-uniform: planes away from walls take no per-direction selects
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
-      const bool bounce = (cz > 0 && lo) || (cz < 0 && hi);
-      if (bounce) {
-        const T* b = src + (size_t)L::opp[i] * (size_t)N;
-        f[i] = St::dec(b[zo + yo + x], shift[L::opp[i]]);
-      } else {
-        const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
-        const int sy = cy > 0 ? yom : (cy < 0 ? yop : yo);
-        const int sz = cz > 0 ? zom : (cz < 0 ? zop : zo);
-        const T* b = src + (size_t)i * (size_t)N;
-        f[i] = St::dec(b[sz + sy + sx], shift[i]);
+      for (int i = 0; i < Q; ++i) {
+        const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
+        const char* b = cz > 0 ? bm : (cz < 0 ? bp : b0);
+        f[i] = St::dec(gld<T>(b + i * 128, oxy[(cx + 1) + 3 * (cy + 1)]), shift[i]);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
+        const bool bounce = (cz > 0 && lo) || (cz < 0 && hi);
+        const int o = L::opp[i];
+        const char* b = bounce ? b0 + o * 128 : (cz > 0 ? bm : (cz < 0 ? bp : b0)) + i * 128;
+        const uint32_t off = bounce ? oxy[4] : oxy[(cx + 1) + 3 * (cy + 1)];
+        f[i] = St::dec(gld<T>(b, off), shift[bounce ? o : i]);
       }
     }
   };
@@ -181,218 +384,131 @@ __global__ __launch_bounds__(NT) void k_step(const KParams* __restrict__ P, cons
     return r;
   };
 
-  // plane index helpers: logical plane zl (may be -1 or nz) -> stored plane
-  auto wrapz = [&](int zl) {
-    if (zl < 0) return bbz ? 0 : zl + nz;
-    if (zl >= nz) return bbz ? nz - 1 : zl - nz;
-    return zl;
-  };
-
   bool psi_neg = false;
 
-  // Phase A for logical plane zl: psi of tile + halo into LDS slot; interior
-  // populations into fout (when keep) and rho into rout.
-  auto phaseA = [&](int zl, bool keep, C (*fout)[Q], C* rout) {
+  // Phase A for logical plane zl: psi of tile + halo into the LDS ring; the
+  // interior populations and rho into fo / ro.
+  auto phaseA = [&](int zl, bool keep, C* fo, C& ro) {
     const int pz = wrapz(zl);
-    const int zo = pz * plane;
-    const int zom = (pz == 0 ? (bbz ? 0 : nz - 1) : pz - 1) * plane;
-    const int zop = (pz == nz - 1 ? (bbz ? nz - 1 : 0) : pz + 1) * plane;
+    const int zm = pz == 0 ? (bbz ? 0 : nz - 1) : pz - 1;
+    const int zp = pz == nz - 1 ? (bbz ? nz - 1 : 0) : pz + 1;
+    const char* b0 = src + (uint64_t)pz * zblock;
+    const char* bm = src + (uint64_t)zm * zblock;
+    const char* bp = src + (uint64_t)zp * zblock;
     const bool lo = bbz && pz == 0;
     const bool hi = bbz && pz == nz - 1;
     C* sl = lds_psi + ((zl - z0 + 1) & 3) * PL;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      C f[Q];
-      pull(ix[s], ixm[s], ixp[s], iyo[s], iyom[s], iyop[s], zo, zom, zop, lo, hi, f);
-      C r = density(f);
+    pull(ioxy, bm, b0, bp, lo, hi, fo);
+    if (hact) {
+      C hf[Q];
+      pull(hoxy, bm, b0, bp, lo, hi, hf);
       bool ng;
-      double ps = psi_of_rho(p, (double)r, &ng);
-      psi_neg |= ng && ivalid[s] && keep;
-      sl[ilds[s]] = (C)ps;
-      if (keep) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) fout[s][i] = f[i];
-        rout[s] = r;
-      }
+      sl[hlds] = psi_eval<C>(eos, (double)density(hf), &ng);
     }
-#pragma unroll
-    for (int k = 0; k < HPT; ++k) {
-      if (hact[k]) {
-        C f[Q];
-        pull(hx[k], hxm[k], hxp[k], hyo[k], hyom[k], hyop[k], zo, zom, zop, lo, hi, f);
-        bool ng;
-        sl[hlds[k]] = (C)psi_of_rho(p, (double)density(f), &ng);
-      }
-    }
+    const C r = density(fo);
+    ro = r;
+    bool ng;
+    sl[ilds] = psi_eval<C>(eos, (double)r, &ng);
+    psi_neg |= ng && ivalid && keep;
   };
 
   // force coefficients: F = cA psi M1 + cB (M1.M2) + cC M1 tr(M2) + Fg
-  const C cA = (C)(-p.G);
-  const C cB = (C)(p.G / 4.0 * p.eps - p.G / 6.0 * (p.kappa - 1.0));
-  const C cC = (C)(p.G / 6.0 * (p.kappa - 1.0));
+  const double G = kp->G, eps_ = kp->eps, kap = kp->kappa;
+  const C cA = (C)(-G);
+  const C cB = (C)(G / 4.0 * eps_ - G / 6.0 * (kap - 1.0));
+  const C cC = (C)(G / 6.0 * (kap - 1.0));
   C Fg[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) Fg[a] = (C)p.Fg[a];
-  const C tau_v = (C)p.tau_v, tau_slope = (C)p.tau_slope, rho_v = (C)p.rho_v;
+  for (int a = 0; a < D; ++a) Fg[a] = (C)kp->Fg[a];
+  const C tau_v = (C)kp->tau_v, tau_slope = (C)kp->tau_slope, rho_v = (C)kp->rho_v;
   C rate[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) rate[k] = (C)p.rates[k];
+  for (int k = 0; k < 4; ++k) rate[k] = (C)kp->rates[k];
+  float* const uprev = kp->uprev;
 
   // reduction accumulators
   double acc_ms = 0.0, acc_mc = 0.0, acc_mom[3] = {0.0, 0.0, 0.0}, acc_umax = 0.0, acc_dumax = 0.0;
   int acc_flags = 0;
 
-  C fc[S][Q], fn[S][Q];
-  C rc[S], rn[S];
-
-  phaseA(z0 - 1, false, fn, rn);
-  phaseA(z0, true, fc, rc);
-
-  for (int z = z0; z < z1; ++z) {
-    phaseA(z + 1, true, fn, rn);
-    __syncthreads();
+  // Phase B for output plane z with the populations f / rho of that plane.
+  auto phaseB = [&](int z, const C* f, C rho) {
     const C* s_m = lds_psi + ((z - z0) & 3) * PL;
     const C* s_0 = lds_psi + ((z - z0 + 1) & 3) * PL;
     const C* s_p = lds_psi + ((z - z0 + 2) & 3) * PL;
+    C F[D], u[D];
+    stencil_force<L, C, W2>(s_m, s_0, s_p, ilds, cA, cB, cC, Fg, F);
+    // j_a = sum_i f_i c_ia over opposite pairs
+    C dp[L::P];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const C rho = rc[s];
-      const C* f = fc[s];
-      // psi stencil: S0 = sum w psi, S1_a = sum w psi c_a, S2_ab = sum w psi c_a c_b
-      C S0 = 0, S1[D], S2[D][D];
+    for (int p = 0; p < L::P; ++p) dp[p] = f[L::pa[p]] - f[L::pb[p]];
+    const C inv_rho = recip(rho);
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        S1[a] = 0;
+    for (int a = 0; a < D; ++a) {
+      C ja = 0;
 #pragma unroll
-        for (int b = 0; b < D; ++b) S2[a][b] = 0;
+      for (int p = 0; p < L::P; ++p) {
+        if (L::c(L::pa[p], a) > 0) ja += dp[p];
+        if (L::c(L::pa[p], a) < 0) ja -= dp[p];
       }
-      C psi_c = s_0[ilds[s]];
+      u[a] = (ja + (C)0.5 * F[a]) * inv_rho;
+    }
+    const uint32_t nid = (uint32_t)(z * plane + own);  // canonical node index
+    if (MODE == MODE_STEP) {
+      const C omega = recip(tau_v + (rho - rho_v) * tau_slope);
+      C fs[Q];
+      collide<L, C, COLL>(f, dp, rho, u, F, omega, rate, fs);
+      if (ivalid) {
+        char* dz = dst + (uint64_t)z * zblock;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const int cz = L::cz[i];
-        const C* sl = cz > 0 ? s_p : (cz < 0 ? s_m : s_0);
-        const C ps = sl[ilds[s] + L::cy[i] * W2 + L::cx[i]];
-        const C wp = (C)L::w[i] * ps;
-        S0 += wp;
+        for (int i = 0; i < Q; ++i) gst<T>(dz + i * 128, ioxy[4], St::enc(fs[i], shift[i]));
+      }
+    } else if (MODE == MODE_MOMENTS) {
+      if (ivalid) {
+        out_rho[nid] = (double)rho;
+#pragma unroll
+        for (int a = 0; a < D; ++a) out_u[(size_t)a * N + nid] = (double)u[a];
+      }
+    } else {  // MODE_REDUCE
+      if (ivalid) {
+        const double dr = (double)rho;
+        neumaier_add(acc_ms, acc_mc, dr);
+        double usq = 0.0, dsq = 0.0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          if (L::c(i, a) != 0) S1[a] += (C)L::c(i, a) * wp;
-#pragma unroll
-          for (int b = 0; b < D; ++b)
-            if (L::c(i, a) * L::c(i, b) != 0) S2[a][b] += (C)(L::c(i, a) * L::c(i, b)) * wp;
+          const double ua = (double)u[a];
+          acc_mom[a] += dr * ua;
+          usq += ua * ua;
+          float* up = uprev + (size_t)a * N + nid;
+          const double dd = ua - (double)*up;
+          dsq += dd * dd;
+          *up = (float)ua;
         }
+        acc_umax = fmax(acc_umax, sqrt(usq));
+        acc_dumax = fmax(acc_dumax, sqrt(dsq));
+        if (!(dr == dr) || !(usq == usq)) acc_flags |= 1;
+        if (!(dr > 0.0)) acc_flags |= 2;
       }
-      C M1[D], M2[D][D], tr = 0;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        M1[a] = (C)3 * S1[a];
-#pragma unroll
-        for (int b = 0; b < D; ++b) M2[a][b] = (C)9 * S2[a][b] - (a == b ? (C)3 * S0 : (C)0);
-        tr += M2[a][a];
-      }
-      C F[D], j[D], u[D];
-      const C inv_rho = (C)1 / rho;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        C m1m2 = 0;
-#pragma unroll
-        for (int b = 0; b < D; ++b) m1m2 += M1[b] * M2[a][b];
-        F[a] = cA * psi_c * M1[a] + cB * m1m2 + cC * M1[a] * tr + Fg[a];
-        C ja = 0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          if (L::c(i, a) > 0) ja += f[i];
-          if (L::c(i, a) < 0) ja -= f[i];
-        }
-        j[a] = ja;
-        u[a] = (ja + (C)0.5 * F[a]) * inv_rho;
-      }
+    }
+  };
 
-      const int own = z * plane + iyo[s] + ix[s];
-      if (MODE == MODE_STEP) {
-        const C tau = tau_v + (rho - rho_v) * tau_slope;
-        const C omega = (C)1 / tau;
-        C usq = 0, uF = 0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          usq += u[a] * u[a];
-          uF += u[a] * F[a];
-        }
-        C fs[Q], v[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          C cu = 0, cF = 0;
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            if (L::c(i, a) > 0) {
-              cu += u[a];
-              cF += F[a];
-            }
-            if (L::c(i, a) < 0) {
-              cu -= u[a];
-              cF -= F[a];
-            }
-          }
-          const C wi = (C)L::w[i];
-          const C feq = wi * rho * ((C)1 + (C)3 * cu + (C)4.5 * cu * cu - (C)1.5 * usq);
-          const C fh = wi * ((C)3 * cF + (C)9 * cu * cF - (C)3 * uF);
-          v[i] = f[i] - feq + (C)0.5 * fh;
-          fs[i] = f[i] + fh - omega * v[i];
-        }
-        if (COLL == COLL_MRT) {
-          using MC = MrtCorr<L>;
-#pragma unroll
-          for (int k = 0; k < MC::K; ++k) {
-            C mk = 0;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-              if (MC::P(k, i) != 0.0) mk += (C)MC::P(k, i) * v[i];
-            }
-            const C coef = (rate[MC::rate_class[k]] - omega) * (C)(1.0 / mrt_norm<L>(k)) * mk;
-#pragma unroll
-            for (int i = 0; i < Q; ++i)
-              if (MC::P(k, i) != 0.0) fs[i] -= (C)MC::P(k, i) * coef;
-          }
-        }
-        if (ivalid[s]) {
-#pragma unroll
-          for (int i = 0; i < Q; ++i) dst[(size_t)i * (size_t)N + own] = St::enc(fs[i], shift[i]);
-        }
-      } else if (MODE == MODE_MOMENTS) {
-        if (ivalid[s]) {
-          out_rho[own] = (double)rho;
-#pragma unroll
-          for (int a = 0; a < D; ++a) out_u[(size_t)a * (size_t)N + own] = (double)u[a];
-        }
-      } else {  // MODE_REDUCE
-        if (ivalid[s]) {
-          const double dr = (double)rho;
-          neumaier_add(acc_ms, acc_mc, dr);
-          double usq = 0.0, dsq = 0.0;
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            const double ua = (double)u[a];
-            acc_mom[a] += dr * ua;
-            usq += ua * ua;
-            float* up = p.uprev + (size_t)a * (size_t)N + own;
-            const double d = ua - (double)*up;
-            dsq += d * d;
-            *up = (float)ua;
-          }
-          acc_umax = fmax(acc_umax, sqrt(usq));
-          acc_dumax = fmax(acc_dumax, sqrt(dsq));
-          if (!(dr == dr) || !(usq == usq)) acc_flags |= 1;
-          if (!(dr > 0.0)) acc_flags |= 2;
-        }
-      }
-    }
-    // rotate the register pipeline: plane z+1 becomes the current plane
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      rc[s] = rn[s];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) fc[s][i] = fn[s][i];
-    }
+  // The march: two population register sets alternate roles (no copies).
+  C fa[Q], fb[Q];
+  C ra, rb;
+  phaseA(z0 - 1, false, fb, rb);
+  phaseA(z0, true, fa, ra);
+  int z = z0;
+  for (; z + 1 < z1; z += 2) {
+    phaseA(z + 1, true, fb, rb);
+    __syncthreads();
+    phaseB(z, fa, ra);
+    phaseA(z + 2, true, fa, ra);
+    __syncthreads();
+    phaseB(z + 1, fb, rb);
+  }
+  if (z < z1) {
+    phaseA(z + 1, true, fb, rb);
+    __syncthreads();
+    phaseB(z, fa, ra);
   }
 
   if (MODE == MODE_REDUCE) {
@@ -419,7 +535,7 @@ __global__ __launch_bounds__(NT) void k_step(const KParams* __restrict__ P, cons
         o.max_du = fmax(o.max_du, q.max_du);
         o.flags = (double)((int)o.flags | (int)q.flags);
       }
-      reinterpret_cast<RedRec*>(p.red)[tile] = o;
+      reinterpret_cast<RedRec*>(kp->red)[tile] = o;
     }
   }
 }

@@ -120,7 +120,7 @@ def load(path=None):
         import torch  # noqa: F401  (loads the HIP runtime the library links against)
     except ImportError:
         pass
-    p = path or LIB_PATH
+    p = path or os.environ.get("PLBM_LIB") or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"{p} is not built: run `python -m paper_2504_15018_amd.build` (the HIP library is "
                            "required; there is no CPU fallback)")
