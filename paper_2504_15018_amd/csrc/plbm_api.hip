@@ -50,7 +50,8 @@ struct Layout {
   int nxk, nyk, nzk;  // kernel axes
   int tx, ty, cz, tiles_x, tiles_y, tiles_z, ntiles;
   int nxb;         // 128-byte x blocks per row of stored populations
-  uint64_t zblock; // bytes of one z plane of stored populations
+  uint64_t zdata;  // bytes of node data of one z plane of stored populations
+  uint64_t zblock; // zdata plus a trash area for the ragged-tile lanes of one workgroup
   int64_t N;
   uint64_t popA, popB, aux, uprev, red, kp, total;
 };
@@ -60,10 +61,12 @@ int choose_cz(int nzk, int tiles_xy) {
     int v = std::atoi(e);
     if (v > 0) return v < nzk ? v : nzk;
   }
-  int64_t target = 1024;
+  // about 512 workgroups (two per CU); long chunks amortise the two extra
+  // planes each chunk recomputes
+  int64_t target = 512;
   int64_t cz = ((int64_t)nzk * tiles_xy + target - 1) / target;
   if (cz < 4) cz = 4;
-  if (cz > 64) cz = 64;
+  if (cz > 128) cz = 128;
   if (cz > nzk) cz = nzk;
   return (int)cz;
 }
@@ -101,7 +104,9 @@ int make_layout(const plbm_lattice_desc* d, Layout* L) {
   const uint64_t S = storage_bytes(d->storage);
   const int XB = (int)(128 / S);
   L->nxb = (L->nxk + XB - 1) / XB;
-  L->zblock = (uint64_t)L->nyk * L->nxb * L->Q * 128;
+  L->zdata = (uint64_t)L->nyk * L->nxb * L->Q * 128;
+  const int nthr = L->tx * L->ty;  // threads per workgroup (one node each)
+  L->zblock = L->zdata + (uint64_t)((nthr + XB - 1) / XB) * L->Q * 128;
   if (L->zblock >= (1ull << 31)) return set_error(PLBM_E_UNSUPPORTED, "one z plane of populations exceeds 2 GiB");
   uint64_t off = 0;
   L->popA = off;
@@ -167,6 +172,7 @@ int run_step_kernel(plbm_lattice* L, int mode, int phase, double* orho, double* 
   a.lattice = L->desc.lattice;
   a.coll = L->desc.collision;
   a.mode = mode;
+  a.walls = L->kp.bb_z;
   a.nblocks = L->lay.ntiles;
   a.stream = L->stream;
   a.P = L->kp_dev;
@@ -242,6 +248,7 @@ void fill_kparams(plbm_lattice* L) {
   k.parity = 0;
   k.nxb = y.nxb;
   k.zblock = (int64_t)y.zblock;
+  k.zdata = (int64_t)y.zdata;
 }
 
 int check_lat(plbm_lattice* L) { return L ? PLBM_OK : set_error(PLBM_E_INVALID, "null lattice"); }
@@ -256,7 +263,7 @@ int capture_graph2(plbm_lattice* L) {
   if (st != PLBM_OK) return st;
   if (e != hipSuccess) return set_error(PLBM_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
   e = hipGraphInstantiate(&L->graph2, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) return set_error(PLBM_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
   L->has_graph = true;
   return PLBM_OK;
@@ -493,7 +500,7 @@ int plbm_reduce(plbm_lattice* L, plbm_diag* out) {
 
 void plbm_destroy(plbm_lattice* L) {
   if (!L) return;
-  if (L->has_graph) hipGraphExecDestroy(L->graph2);
+  if (L->has_graph) (void)hipGraphExecDestroy(L->graph2);
   delete L;
 }
 
@@ -511,7 +518,7 @@ struct plbm_batch {
   WorkItem* work_dev;
   std::vector<plbm_lattice*> lat;
   struct Group {
-    int lattice, coll, storage;
+    int lattice, coll, storage, walls;
     int offset, count;  // segment of the work table
   };
   std::vector<Group> groups;
@@ -535,25 +542,26 @@ uint64_t batch_layout(int max_slots, int64_t max_tiles, uint64_t* off_work) {
 int batch_rebuild(plbm_batch* b) {
   if (!b->dirty) return PLBM_OK;
   if (b->has_graph) {
-    hipGraphExecDestroy(b->graph2);
+    (void)hipGraphExecDestroy(b->graph2);
     b->has_graph = false;
   }
   b->groups.clear();
   b->work_host.clear();
-  std::map<std::tuple<int, int, int>, std::vector<int>> by_type;
+  std::map<std::tuple<int, int, int, int>, std::vector<int>> by_type;
   for (int s = 0; s < b->max_slots; ++s) {
     plbm_lattice* L = b->lat[s];
     if (!L) continue;
     KParams k = L->kp;
     k.parity = (int)(L->t & 1);
     b->slots_host[s] = k;
-    by_type[std::make_tuple(L->desc.lattice, L->desc.collision, L->desc.storage)].push_back(s);
+    by_type[std::make_tuple(L->desc.lattice, L->desc.collision, L->desc.storage, L->kp.bb_z)].push_back(s);
   }
   for (auto& kv : by_type) {
     plbm_batch::Group gr;
     gr.lattice = std::get<0>(kv.first);
     gr.coll = std::get<1>(kv.first);
     gr.storage = std::get<2>(kv.first);
+    gr.walls = std::get<3>(kv.first);
     gr.offset = (int)b->work_host.size();
     for (int s : kv.second)
       for (int t = 0; t < b->lat[s]->lay.ntiles; ++t) b->work_host.push_back(WorkItem{s, t});
@@ -580,6 +588,7 @@ int batch_launch(plbm_batch* b, int mode, int phase) {
     a.lattice = gr.lattice;
     a.coll = gr.coll;
     a.mode = mode;
+    a.walls = gr.walls;
     a.nblocks = gr.count;
     a.stream = b->stream;
     a.P = b->slots_dev;
@@ -666,7 +675,7 @@ int plbm_batch_step(plbm_batch* b, int64_t n) {
       if (s1) return s1;
       if (e != hipSuccess) return set_error(PLBM_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
       e = hipGraphInstantiate(&b->graph2, gr, nullptr, nullptr, 0);
-      hipGraphDestroy(gr);
+      (void)hipGraphDestroy(gr);
       if (e != hipSuccess) return set_error(PLBM_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
       b->has_graph = true;
     }
@@ -714,7 +723,7 @@ int plbm_batch_diag(plbm_batch* b, plbm_diag* per_slot) {
 
 void plbm_batch_destroy(plbm_batch* b) {
   if (!b) return;
-  if (b->has_graph) hipGraphExecDestroy(b->graph2);
+  if (b->has_graph) (void)hipGraphExecDestroy(b->graph2);
   delete b;
 }
 

@@ -23,7 +23,8 @@ __device__ __forceinline__ int64_t storage_index(const KParams& p, int i, int x,
   sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
   sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
   sz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
-  return ((((int64_t)sz * ny + sy) * p.nxb + sx / XB) * L::Q + q) * XB + sx % XB;
+  // z planes are zblock bytes apart (node data followed by a trash area)
+  return (int64_t)sz * (p.zblock / (int64_t)sizeof(T)) + (((int64_t)sy * p.nxb + sx / XB) * L::Q + q) * XB + sx % XB;
 }
 
 // Direction whose storage slot holds f_i(x) (differs from i only at walls).

@@ -122,6 +122,7 @@ struct MrtInvNorm {
 struct StF64 {
   using T = double;
   using C = double;  // arithmetic type
+  static constexpr bool shifted = false;
   static __device__ __forceinline__ C dec(T v, C) { return v; }
   static __device__ __forceinline__ T enc(C f, C) { return f; }
   static __device__ __forceinline__ double dec64(T v, double) { return v; }
@@ -131,6 +132,7 @@ struct StF64 {
 struct StF32 {
   using T = float;
   using C = float;
+  static constexpr bool shifted = false;
   static __device__ __forceinline__ C dec(T v, C) { return v; }
   static __device__ __forceinline__ T enc(C f, C) { return f; }
   static __device__ __forceinline__ double dec64(T v, double) { return (double)v; }
@@ -140,6 +142,7 @@ struct StF32 {
 struct StF16S {
   using T = _Float16;
   using C = float;
+  static constexpr bool shifted = true;
   static __device__ __forceinline__ C dec(T v, C shift) { return (float)v + shift; }
   static __device__ __forceinline__ T enc(C f, C shift) { return (_Float16)(f - shift); }  // RNE
   static __device__ __forceinline__ double dec64(T v, double shift) { return (double)(float)v + shift; }
@@ -149,6 +152,7 @@ struct StF16S {
 struct StBF16S {
   using T = uint16_t;  // bfloat16 bit pattern
   using C = float;
+  static constexpr bool shifted = true;
   static __device__ __forceinline__ C dec(T v, C shift) {
     return __uint_as_float(((uint32_t)v) << 16) + shift;
   }
@@ -193,7 +197,8 @@ struct KParams {
   double rho0_shift;
   int32_t parity;  // batch slots: A-B phase offset of this lattice
   int32_t nxb;     // x blocks of one 128-byte line per row (storage layout)
-  int64_t zblock;  // bytes of one z plane of stored populations
+  int64_t zblock;  // bytes of one z plane of stored populations (node data + trash)
+  int64_t zdata;   // bytes of the node data of one z plane
 };
 
 // Stored population layout: A[z][y][x / XB][q][x % XB] with XB = 128 / sizeof(T),

@@ -11,8 +11,12 @@ namespace plbm {
 template <class L, int COLL, int MODE>
 static hipError_t go_step(const StepLaunch& a) {
   using TS = TileShape<L>;
-  hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, TS::NT>), dim3(a.nblocks), dim3(TS::NT), 0,
-                     a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
+  if (a.walls)
+    hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, TS::NT, true>), dim3(a.nblocks), dim3(TS::NT),
+                       0, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
+  else
+    hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, TS::NT, false>), dim3(a.nblocks),
+                       dim3(TS::NT), 0, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
   return hipGetLastError();
 }
 

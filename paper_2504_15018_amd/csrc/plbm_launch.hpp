@@ -17,9 +17,12 @@ struct ShapeK;
 // (one node per thread per plane); D2Q9 rows of 128 nodes per 128 threads.
 template <class L>
 struct TileShape;
+#ifndef PLBM_D3_TY
+#define PLBM_D3_TY 8
+#endif
 template <>
 struct TileShape<D3Q19L> {
-  static constexpr int TX = 32, TY = 8, NT = 256;
+  static constexpr int TX = 32, TY = PLBM_D3_TY, NT = 32 * PLBM_D3_TY;
 };
 template <>
 struct TileShape<D2Q9L> {
@@ -30,6 +33,7 @@ struct StepLaunch {
   int lattice;  // 0 D2Q9, 1 D3Q19
   int coll;     // 0 BGK, 1 MRT
   int mode;     // 0 step, 1 moments, 2 reduce
+  int walls;    // half-way bounce-back on the marching axis
   int nblocks;
   hipStream_t stream;
   const KParams* P;

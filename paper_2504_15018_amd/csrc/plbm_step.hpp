@@ -230,10 +230,16 @@ __device__ __forceinline__ void collide(const C* f, const C* dp, C rho, const C*
   fs[0] = om1 * f[0] + B0;
 }
 
-template <class L, class St, int COLL, int MODE, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __restrict__ P, const WorkItem* __restrict__ work,
-                                             int32_t nwork, int32_t phase, double* __restrict__ out_rho,
-                                             double* __restrict__ out_u) {
+template <bool B>
+struct BoolC {
+  static constexpr bool value = B;
+};
+
+template <class L, class St, int COLL, int MODE, int TX, int TY, int NT, bool WALLS>
+__global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __restrict__ P,
+                                                             const WorkItem* __restrict__ work, int32_t nwork,
+                                                             int32_t phase, double* __restrict__ out_rho,
+                                                             double* __restrict__ out_u) {
   using T = typename St::T;
   using C = typename St::C;
   constexpr int Q = L::Q, D = L::D, HY = L::HY;
@@ -241,10 +247,12 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   constexpr int W2 = TX + 2;
   constexpr int PL = W2 * (TY + 2 * HY);  // LDS plane (tile + halo)
   constexpr int H = PL - TX * TY;         // halo nodes per plane
+  constexpr int HW = (H + 63) / 64;       // waves that carry the halo ring
   static_assert(H <= NT, "halo fits one node per thread");
   constexpr uint32_t TS = sizeof(T);
+  constexpr int XB = Lines<T>::XB;
 
-  __shared__ C lds_psi[4 * PL];
+  __shared__ C lds_psi[4 * PL + 64];  // 4-plane psi ring + a slot per lane for idle halo lanes
   __shared__ RedRec red_lds[(MODE == MODE_REDUCE) ? NT : 1];
 
   int wid = xcd_remap(blockIdx.x, gridDim.x);
@@ -259,9 +267,9 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
 
   const int nx = kp->nx, ny = kp->ny, nz = kp->nz;
   const uint32_t N = (uint32_t)kp->N;
-  constexpr int XB = Lines<T>::XB;
   const int nxb = kp->nxb;
-  const uint64_t zblock = (uint64_t)kp->zblock;  // bytes of one z plane of populations
+  const uint64_t zblock = (uint64_t)kp->zblock;  // bytes of one z plane of stored populations
+  const uint32_t zdata = (uint32_t)kp->zdata;    // bytes of its node data (a trash area follows)
   const int tiles_x = kp->tiles_x, tiles_y = kp->tiles_y, czc = kp->cz;
   const int txi = tile % tiles_x;
   const int tyi = (tile / tiles_x) % tiles_y;
@@ -274,7 +282,6 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   const char* const src = par ? pop1 : pop0;
   char* const dst = par ? pop0 : pop1;
   const int plane = nx * ny;
-  const bool bbz = kp->bb_z != 0;
   const EosK eos = load_eos(kp);
   const double rho0_shift = kp->rho0_shift;
 
@@ -287,12 +294,14 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   // populations, of direction 0 of the pull source (x - cx, y - cy);
   // direction q adds q * 128 bytes.
   const int t = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(t) >> 6;
   auto node_off = [&](int x, int y) -> uint32_t {
     return (uint32_t)((((y * nxb + x / XB) * Q) * XB + x % XB) * (int)TS);
   };
   uint32_t ioxy[9], hoxy[9];
+  uint32_t soff;  // store offset: own node, or the trash area for ragged-tile lanes
   int ilds, hlds, own;
-  bool ivalid, hact;
+  bool ivalid;
   {
     const int lx = t % TX, ly = t / TX;
     int gx = x0 + lx, gy = y0 + ly;
@@ -309,10 +318,13 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
             node_off(cx > 0 ? xm : (cx < 0 ? xp : gx), cy > 0 ? ym : (cy < 0 ? yp : gy));
     ilds = (ly + HY) * W2 + (lx + 1);
     own = gy * nx + gx;
+    soff = ivalid ? ioxy[4] : zdata + (uint32_t)((((t / XB) * Q) * XB + t % XB) * (int)TS);
   }
   {
+    // halo node h = t of the ring around the tile; lanes t >= H of the halo
+    // waves repeat their own node and write psi to a spare LDS slot
     const int h = t;
-    hact = h < H;
+    const bool hact = h < H;
     int lx, ly;
     if (HY) {
       if (h < W2) {
@@ -330,49 +342,51 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
       lx = (h & 1) ? TX : -1;
       ly = 0;
     }
-    if (!hact) {
-      lx = 0;
-      ly = 0;
+    if (hact) {
+      const int gx = ((x0 + lx) % nx + nx) % nx;  // periodic in x and y
+      const int gy = ((y0 + ly) % ny + ny) % ny;
+      const int xm = gx == 0 ? nx - 1 : gx - 1, xp = gx == nx - 1 ? 0 : gx + 1;
+      const int ym = gy == 0 ? ny - 1 : gy - 1, yp = gy == ny - 1 ? 0 : gy + 1;
+#pragma unroll
+      for (int cy = -1; cy <= 1; ++cy)
+#pragma unroll
+        for (int cx = -1; cx <= 1; ++cx)
+          hoxy[(cx + 1) + 3 * (cy + 1)] =
+              node_off(cx > 0 ? xm : (cx < 0 ? xp : gx), cy > 0 ? ym : (cy < 0 ? yp : gy));
+      hlds = (ly + HY) * W2 + (lx + 1);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) hoxy[c] = ioxy[c];
+      hlds = 4 * PL + (t & 63);
     }
-    const int gx = ((x0 + lx) % nx + nx) % nx;  // periodic in x and y
-    const int gy = ((y0 + ly) % ny + ny) % ny;
-    const int xm = gx == 0 ? nx - 1 : gx - 1, xp = gx == nx - 1 ? 0 : gx + 1;
-    const int ym = gy == 0 ? ny - 1 : gy - 1, yp = gy == ny - 1 ? 0 : gy + 1;
-#pragma unroll
-    for (int cy = -1; cy <= 1; ++cy)
-#pragma unroll
-      for (int cx = -1; cx <= 1; ++cx)
-        hoxy[(cx + 1) + 3 * (cy + 1)] =
-            node_off(cx > 0 ? xm : (cx < 0 ? xp : gx), cy > 0 ? ym : (cy < 0 ? yp : gy));
-    hlds = (ly + HY) * W2 + (lx + 1);
   }
 
   // logical plane zl (may be -1 or nz) -> stored plane
   auto wrapz = [&](int zl) {
-    if (zl < 0) return bbz ? 0 : zl + nz;
-    if (zl >= nz) return bbz ? nz - 1 : zl - nz;
+    if (zl < 0) return WALLS ? 0 : zl + nz;
+    if (zl >= nz) return WALLS ? nz - 1 : zl - nz;
     return zl;
   };
 
   // Pull the Q populations of one node of stored plane pz; bm, b0, bp are
-  // the population blocks of the planes pz-1, pz, pz+1.
+  // the population blocks of the planes pz-1, pz, pz+1.  With walls on the
+  // marching axis, a population whose source lies beyond the wall is the
+  // opposite population of the same node (half-way bounce-back); the choice
+  // is wave-uniform and made by selects, keeping the loop free of branches.
   auto pull = [&](const uint32_t* oxy, const char* bm, const char* b0, const char* bp, bool lo, bool hi, C* f) {
-    if (!(lo || hi)) {  // wave-uniform: planes away from walls take no per-direction selects
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
-        const char* b = cz > 0 ? bm : (cz < 0 ? bp : b0);
-        f[i] = St::dec(gld<T>(b + i * 128, oxy[(cx + 1) + 3 * (cy + 1)]), shift[i]);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
-        const bool bounce = (cz > 0 && lo) || (cz < 0 && hi);
+    for (int i = 0; i < Q; ++i) {
+      const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
+      const char* b = (cz > 0 ? bm : (cz < 0 ? bp : b0)) + i * 128;
+      const uint32_t off = oxy[(cx + 1) + 3 * (cy + 1)];
+      if (WALLS && cz != 0) {
+        const bool bounce = cz > 0 ? lo : hi;
         const int o = L::opp[i];
-        const char* b = bounce ? b0 + o * 128 : (cz > 0 ? bm : (cz < 0 ? bp : b0)) + i * 128;
-        const uint32_t off = bounce ? oxy[4] : oxy[(cx + 1) + 3 * (cy + 1)];
-        f[i] = St::dec(gld<T>(b, off), shift[bounce ? o : i]);
+        const C v = St::dec(gld<T>(bounce ? b0 + o * 128 : b, bounce ? oxy[4] : off), (C)0);
+        f[i] = v + (bounce ? shift[o] : shift[i]);
+        if (!St::shifted) f[i] = v;
+      } else {
+        f[i] = St::dec(gld<T>(b, off), shift[i]);
       }
     }
   };
@@ -386,30 +400,37 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
 
   bool psi_neg = false;
 
-  // Phase A for logical plane zl: psi of tile + halo into the LDS ring; the
-  // interior populations and rho into fo / ro.
-  auto phaseA = [&](int zl, bool keep, C* fo, C& ro) {
+  // Phase A, split in two so that a plane's loads are in flight while the
+  // previous plane is collided: issue() pulls the populations of logical
+  // plane zl (tile node into fo, halo node into ho); finish() sums rho and
+  // writes psi of the tile and the halo ring into the LDS ring.
+  auto issue = [&](auto halo_c, int zl, C* fo, C* ho) {
+    constexpr bool HALO = decltype(halo_c)::value;
     const int pz = wrapz(zl);
-    const int zm = pz == 0 ? (bbz ? 0 : nz - 1) : pz - 1;
-    const int zp = pz == nz - 1 ? (bbz ? nz - 1 : 0) : pz + 1;
+    const int zm = pz == 0 ? (WALLS ? 0 : nz - 1) : pz - 1;
+    const int zp = pz == nz - 1 ? (WALLS ? nz - 1 : 0) : pz + 1;
     const char* b0 = src + (uint64_t)pz * zblock;
     const char* bm = src + (uint64_t)zm * zblock;
     const char* bp = src + (uint64_t)zp * zblock;
-    const bool lo = bbz && pz == 0;
-    const bool hi = bbz && pz == nz - 1;
-    C* sl = lds_psi + ((zl - z0 + 1) & 3) * PL;
+    const bool lo = WALLS && pz == 0;
+    const bool hi = WALLS && pz == nz - 1;
     pull(ioxy, bm, b0, bp, lo, hi, fo);
-    if (hact) {
-      C hf[Q];
-      pull(hoxy, bm, b0, bp, lo, hi, hf);
-      bool ng;
-      sl[hlds] = psi_eval<C>(eos, (double)density(hf), &ng);
-    }
+    if constexpr (HALO) pull(hoxy, bm, b0, bp, lo, hi, ho);
+  };
+  auto finish = [&](auto halo_c, int zl, bool keep, const C* fo, C& ro, const C* ho) {
+    constexpr bool HALO = decltype(halo_c)::value;
+    C* sl = lds_psi + ((zl - z0 + 1) & 3) * PL;
     const C r = density(fo);
     ro = r;
     bool ng;
     sl[ilds] = psi_eval<C>(eos, (double)r, &ng);
     psi_neg |= ng && ivalid && keep;
+    if constexpr (HALO) {
+      bool hng;
+      const C ph = psi_eval<C>(eos, (double)density(ho), &hng);
+      // the spare slots of idle lanes sit past the ring
+      (hlds < 4 * PL ? sl : lds_psi)[hlds] = ph;
+    }
   };
 
   // force coefficients: F = cA psi M1 + cB (M1.M2) + cC M1 tr(M2) + Fg
@@ -457,11 +478,9 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
       const C omega = recip(tau_v + (rho - rho_v) * tau_slope);
       C fs[Q];
       collide<L, C, COLL>(f, dp, rho, u, F, omega, rate, fs);
-      if (ivalid) {
-        char* dz = dst + (uint64_t)z * zblock;
+      char* dz = dst + (uint64_t)z * zblock;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) gst<T>(dz + i * 128, ioxy[4], St::enc(fs[i], shift[i]));
-      }
+      for (int i = 0; i < Q; ++i) gst<T>(dz + i * 128, soff, St::enc(fs[i], shift[i]));
     } else if (MODE == MODE_MOMENTS) {
       if (ivalid) {
         out_rho[nid] = (double)rho;
@@ -491,25 +510,43 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     }
   };
 
-  // The march: two population register sets alternate roles (no copies).
-  C fa[Q], fb[Q];
-  C ra, rb;
-  phaseA(z0 - 1, false, fb, rb);
-  phaseA(z0, true, fa, ra);
-  int z = z0;
-  for (; z + 1 < z1; z += 2) {
-    phaseA(z + 1, true, fb, rb);
-    __syncthreads();
-    phaseB(z, fa, ra);
-    phaseA(z + 2, true, fa, ra);
-    __syncthreads();
-    phaseB(z + 1, fb, rb);
-  }
-  if (z < z1) {
-    phaseA(z + 1, true, fb, rb);
-    __syncthreads();
-    phaseB(z, fa, ra);
-  }
+  // The march, specialised per wave (the waves holding the halo ring and the
+  // others run separate branch-free loops with the same barriers).  Three
+  // population register sets rotate roles (unrolled by three, no copies):
+  // plane z is collided while plane z+1 waits with its psi in LDS and the
+  // loads of plane z+2 are in flight.
+  auto march = [&](auto halo_c) {
+    C f0[Q], f1[Q], f2[Q], hb[Q];
+    C r0, r1, r2;
+    issue(halo_c, z0 - 1, f0, hb);
+    finish(halo_c, z0 - 1, false, f0, r0, hb);
+    issue(halo_c, z0, f0, hb);
+    finish(halo_c, z0, true, f0, r0, hb);
+    issue(halo_c, z0 + 1, f1, hb);
+    finish(halo_c, z0 + 1, true, f1, r1, hb);
+    // loads of z+2 into pf, barrier, collide z, psi of z+2
+    auto stepz = [&](int z, C* cur, C rc, C* pf, C& rp) {
+      issue(halo_c, z + 2, pf, hb);
+      __syncthreads();
+      phaseB(z, cur, rc);
+      finish(halo_c, z + 2, true, pf, rp, hb);
+    };
+    int z = z0;
+    for (; z + 2 < z1; z += 3) {
+      stepz(z, f0, r0, f2, r2);
+      stepz(z + 1, f1, r1, f0, r0);
+      stepz(z + 2, f2, r2, f1, r1);
+    }
+    if (z < z1) {
+      stepz(z, f0, r0, f2, r2);
+      ++z;
+    }
+    if (z < z1) stepz(z, f1, r1, f0, r0);
+  };
+  if (wave < HW)
+    march(BoolC<true>{});
+  else
+    march(BoolC<false>{});
 
   if (MODE == MODE_REDUCE) {
     if (psi_neg) acc_flags |= 4;
