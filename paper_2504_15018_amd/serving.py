@@ -1,0 +1,209 @@
+"""Continuous-batching request loop for P-LBM solves (plbm_batch_*).
+
+A request asks for one static-droplet solve: lattice kind and size, reduced
+temperature of the lattice Peng-Robinson EOS, droplet radius.  The loop
+
+  * admits queued requests in arrival order while a batch slot is free and the
+    device bytes of every resident lattice (plbm_lattice_bytes) plus the new
+    one stay within the HBM budget; a request that does not fit waits;
+  * gives each admitted request its own lattice (a PyTorch device buffer),
+    initialised on the device (plbm_init_shape) and attached to the batch;
+  * advances every resident lattice together with plbm_batch_step (one launch
+    per lattice type per step, replayed from a captured HIP graph);
+  * every `check_every` steps reads the per-lattice diagnostics
+    (plbm_batch_diag): a lattice whose residual max|u(t) - u(t-k)|/k is at or
+    below `tol` is converged; NaN or rho <= 0 marks it failed; a lattice that
+    reaches `max_steps` is capped.  Finished lattices are detached and their
+    memory released at once, so queued requests can take their place.
+
+Every lattice's result is bitwise the same as stepping it alone: the batch
+only changes which workgroup computes which tile.
+"""
+import time
+
+import numpy as np
+
+from . import native as N
+from .lattice import Lattice
+
+
+class Request:
+    def __init__(self, rid, arrival, lattice, dims, T_over_Tc, radius):
+        self.id = rid
+        self.arrival = float(arrival)
+        self.lattice = lattice
+        self.dims = tuple(int(v) for v in dims)
+        self.T_over_Tc = float(T_over_Tc)
+        self.radius = float(radius)
+        self.admit = None
+        self.done = None
+        self.steps = 0
+        self.status = "queued"
+        self.bytes = 0
+        self.residual = None
+        self.lat = None
+        self.slot = None
+        self.params = None
+
+    @property
+    def nodes(self):
+        return int(np.prod(self.dims))
+
+    def record(self):
+        return {"id": self.id, "arrival": self.arrival, "admit": self.admit, "done": self.done,
+                "latency": None if self.done is None else self.done - self.arrival, "steps": self.steps,
+                "status": self.status, "bytes": self.bytes, "nodes": self.nodes, "lattice": self.lattice,
+                "dims": self.dims, "T_over_Tc": self.T_over_Tc, "residual": self.residual}
+
+
+def admissible(queue, n_resident, used, budget, max_slots):
+    """How many requests at the head of the FIFO queue can be admitted now.
+
+    Arrival order is kept: a head request that does not fit (no free slot, or
+    its bytes would push the resident total over the budget) blocks the ones
+    behind it, so a large request is never starved by smaller later ones."""
+    k = 0
+    for r in queue:
+        if n_resident + k >= max_slots or used + r.bytes > budget:
+            break
+        used += r.bytes
+        k += 1
+    return k
+
+
+def from_synth(reqs):
+    return [Request(r["id"], r["arrival"], r["lattice"], r["dims"], r["T_over_Tc"], r["radius"]) for r in reqs]
+
+
+class Server:
+    def __init__(self, budget_bytes, max_slots=64, max_tiles=1 << 20, check_every=100, tol=1e-8,
+                 max_steps=2_000_000, storage="f32", collision="bgk", keep_lattices=False, width=5.0):
+        import torch
+
+        self.torch = torch
+        self.budget = int(budget_bytes)
+        self.max_slots = max_slots
+        self.check_every = int(check_every)
+        self.tol = tol
+        self.max_steps = int(max_steps)
+        self.storage = storage
+        self.collision = collision
+        self.keep = keep_lattices
+        self.width = width
+        self.stream = torch.cuda.Stream()
+        nb = N.plbm_batch_bytes(max_slots, max_tiles)
+        self._bmem = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+        ptr = (self._bmem.data_ptr() + 255) // 256 * 256
+        self.batch = N.plbm_batch_create(max_slots, max_tiles, ptr, nb, self.stream.cuda_stream)
+        self.resident = {}  # slot -> Request
+        self.used = 0
+        self.peak_used = 0
+        self.peak_resident = 0
+
+    def close(self):
+        self.stream.synchronize()
+        for r in list(self.resident.values()):
+            self._retire(r, "cancelled", time.perf_counter())
+        N.plbm_batch_destroy(self.batch)
+        self.batch = None
+
+    # ---- admission ----
+    def _desc_bytes(self, req):
+        from .lattice import make_desc
+        return N.plbm_lattice_bytes(make_desc(req.lattice, req.dims, self.collision, self.storage)) + 256
+
+    def _admit(self, req, now):
+        req.params = N.plbm_params_pr_lattice(req.T_over_Tc, 0.326, 2.0, 1.0, 1.0, 1.0)
+        lat = Lattice(req.lattice, req.dims, req.params, collision=self.collision, storage=self.storage,
+                      stream=self.stream)
+        centre = [n / 2.0 for n in req.dims]
+        lat.init_shape(N.PLBM_SHAPE_DROPLET, req.params.rho_l, req.params.rho_v, W=self.width, R=req.radius,
+                       centre=centre)
+        lat.reduce()  # stores u(0) for the first residual
+        req.lat = lat
+        req.slot = N.plbm_batch_attach(self.batch, lat.h)
+        req.admit = now
+        req.status = "running"
+        self.resident[req.slot] = req
+        self.used += req.bytes
+        self.peak_used = max(self.peak_used, self.used)
+        self.peak_resident = max(self.peak_resident, len(self.resident))
+
+    def _retire(self, req, status, now):
+        N.plbm_batch_detach(self.batch, req.slot)
+        del self.resident[req.slot]
+        req.status = status
+        req.done = now
+        self.used -= req.bytes
+        if not self.keep:
+            req.lat.close()
+            req.lat = None
+
+    # ---- the loop ----
+    def run(self, requests, time_limit=None, log=None):
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        for r in reqs:
+            r.bytes = self._desc_bytes(r)
+            if r.bytes > self.budget:
+                r.status = "rejected"
+        pending = [r for r in reqs if r.status != "rejected"]
+        queue = []
+        t0 = time.perf_counter()
+        served_updates = 0
+        i = 0
+        while i < len(pending) or queue or self.resident:
+            now = time.perf_counter() - t0
+            if time_limit is not None and now > time_limit:
+                break
+            while i < len(pending) and pending[i].arrival <= now:
+                queue.append(pending[i])
+                i += 1
+            for _ in range(admissible(queue, len(self.resident), self.used, self.budget, self.max_slots)):
+                self._admit(queue.pop(0), time.perf_counter() - t0)
+            if not self.resident:
+                if i < len(pending):
+                    time.sleep(max(0.0, min(pending[i].arrival - now, 0.01)))
+                continue
+            n = self.check_every
+            N.plbm_batch_step(self.batch, n)
+            diag = N.plbm_batch_diag(self.batch, self.max_slots)
+            now = time.perf_counter() - t0
+            for slot, req in list(self.resident.items()):
+                d = diag[slot]
+                req.steps += n
+                served_updates += req.nodes * n
+                req.residual = d.max_du_per_step
+                if d.flags & (N.PLBM_FLAG_NAN | N.PLBM_FLAG_RHO_NONPOS):
+                    self._retire(req, "failed", now)
+                elif req.residual <= self.tol:
+                    self._retire(req, "converged", now)
+                elif req.steps >= self.max_steps:
+                    self._retire(req, "capped", now)
+            if log is not None:
+                log(f"[serve] t={now:.2f}s resident={len(self.resident)} queued={len(queue)} "
+                    f"done={sum(r.done is not None for r in reqs)}/{len(reqs)}")
+        self.stream.synchronize()
+        makespan = time.perf_counter() - t0
+        out = summarize(reqs, makespan, served_updates)
+        out.update(peak_bytes=self.peak_used, peak_resident=self.peak_resident, budget_bytes=self.budget)
+        return out
+
+
+def summarize(reqs, makespan, served_updates):
+    done = [r for r in reqs if r.status == "converged"]
+    lat = np.array([r.done - r.arrival for r in done]) if done else np.array([])
+    pct = (lambda q: float(np.percentile(lat, q))) if len(lat) else (lambda q: None)
+    return {
+        "requests": len(reqs),
+        "converged": len(done),
+        "capped": sum(r.status == "capped" for r in reqs),
+        "failed": sum(r.status == "failed" for r in reqs),
+        "rejected": sum(r.status == "rejected" for r in reqs),
+        "unfinished": sum(r.done is None and r.status != "rejected" for r in reqs),
+        "makespan_s": makespan,
+        "solves_per_s": len(done) / makespan if makespan > 0 else 0.0,
+        "latency_p50_s": pct(50),
+        "latency_p99_s": pct(99),
+        "served_site_updates_per_s": served_updates / makespan if makespan > 0 else 0.0,
+        "records": [r.record() for r in reqs],
+    }
