@@ -27,7 +27,8 @@ COMMON = [
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 SOURCES = {
-    "plbm_k_f64.hip": ["-ffp-contract=off"],
+    # float64 kernels hold twice the registers: one wave per SIMD avoids spills
+    "plbm_k_f64.hip": ["-ffp-contract=off", "-DPLBM_MIN_WAVES=1"],
     "plbm_k_f32.hip": [],
     "plbm_k_f16s.hip": [],
     "plbm_k_bf16s.hip": [],

@@ -102,11 +102,15 @@ int make_layout(const plbm_lattice_desc* d, Layout* L) {
   if (nt > 0x3fffffff) return set_error(PLBM_E_INVALID, "too many tiles");
   L->ntiles = (int)nt;
   const uint64_t S = storage_bytes(d->storage);
-  const int XB = (int)(128 / S);
+  // block width of the population layout (Lines<T> in the kernels)
+  const int XB = (int)(128 / S) < 32 ? (int)(128 / S) : 32;
+  const uint64_t QB = (uint64_t)XB * S;
+  const uint64_t blk = (L->Q * QB + 127) / 128 * 128;  // bytes of one block of XB nodes (Lines<T>::slots)
   L->nxb = (L->nxk + XB - 1) / XB;
-  L->zdata = (uint64_t)L->nyk * L->nxb * L->Q * 128;
+  L->zdata = (uint64_t)L->nyk * L->nxb * blk;
   const int nthr = L->tx * L->ty;  // threads per workgroup (one node each)
-  L->zblock = L->zdata + (uint64_t)((nthr + XB - 1) / XB) * L->Q * 128;
+  // a trash area after each plane takes the stores of ragged-tile lanes
+  L->zblock = L->zdata + (uint64_t)((nthr + XB - 1) / XB) * blk;
   if (L->zblock >= (1ull << 31)) return set_error(PLBM_E_UNSUPPORTED, "one z plane of populations exceeds 2 GiB");
   uint64_t off = 0;
   L->popA = off;

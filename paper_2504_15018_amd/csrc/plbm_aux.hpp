@@ -12,6 +12,7 @@ namespace plbm {
 template <class L, class T>
 __device__ __forceinline__ int64_t storage_index(const KParams& p, int i, int x, int y, int z) {
   constexpr int XB = Lines<T>::XB;
+  constexpr int QS = Lines<T>::template slots<L::Q>();
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   int sz = z - L::cz[i], sx = x - L::cx[i], sy = y - L::cy[i], q = i;
   if (p.bb_z && (sz < 0 || sz >= nz)) {
@@ -24,7 +25,7 @@ __device__ __forceinline__ int64_t storage_index(const KParams& p, int i, int x,
   sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
   sz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
   // z planes are zblock bytes apart (node data followed by a trash area)
-  return (int64_t)sz * (p.zblock / (int64_t)sizeof(T)) + (((int64_t)sy * p.nxb + sx / XB) * L::Q + q) * XB + sx % XB;
+  return (int64_t)sz * (p.zblock / (int64_t)sizeof(T)) + (((int64_t)sy * p.nxb + sx / XB) * QS + q) * XB + sx % XB;
 }
 
 // Direction whose storage slot holds f_i(x) (differs from i only at walls).

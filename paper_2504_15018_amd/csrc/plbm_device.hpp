@@ -201,12 +201,21 @@ struct KParams {
   int64_t zdata;   // bytes of the node data of one z plane
 };
 
-// Stored population layout: A[z][y][x / XB][q][x % XB] with XB = 128 / sizeof(T),
-// so that the innermost unit is one 128-byte line of one direction.  All
-// directions of a node sit at a common offset plus q * 128 bytes.
+// Stored population layout: A[z][y][x / XB][q][x % XB] with XB = 32 nodes
+// (16 for float64), so that the innermost unit, one direction of XB nodes, is
+// QB = XB * sizeof(T) bytes: a 128-byte line for float32 and float64, half a
+// line for 16-bit storage.  A block holds QS >= Q direction slots, QS even for
+// 16-bit storage, so every block starts on a line and a 32-wide tile row
+// covers whole lines that no other tile touches.  All directions of a node sit
+// at a common offset plus q * QB bytes.
 template <class T>
 struct Lines {
-  static constexpr int XB = 128 / (int)sizeof(T);
+  static constexpr int XB = (128 / (int)sizeof(T)) < 32 ? (128 / (int)sizeof(T)) : 32;
+  static constexpr int QB = XB * (int)sizeof(T);
+  template <int Q>
+  static constexpr int slots() {
+    return (Q * QB + 127) / 128 * 128 / QB;
+  }
 };
 
 // Equation-of-state constants held in scalar registers by the kernels.

@@ -251,6 +251,8 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   static_assert(H <= NT, "halo fits one node per thread");
   constexpr uint32_t TS = sizeof(T);
   constexpr int XB = Lines<T>::XB;
+  constexpr int QB = Lines<T>::QB;
+  constexpr int QS = Lines<T>::template slots<Q>();
 
   __shared__ C lds_psi[4 * PL + 64];  // 4-plane psi ring + a slot per lane for idle halo lanes
   __shared__ RedRec red_lds[(MODE == MODE_REDUCE) ? NT : 1];
@@ -292,11 +294,11 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   // ---- node offsets of this thread, fixed for the whole z march ----
   // oxy[(cx+1) + 3 (cy+1)] = byte offset, within a z plane of stored
   // populations, of direction 0 of the pull source (x - cx, y - cy);
-  // direction q adds q * 128 bytes.
+  // direction q adds q * QB bytes.
   const int t = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(t) >> 6;
   auto node_off = [&](int x, int y) -> uint32_t {
-    return (uint32_t)((((y * nxb + x / XB) * Q) * XB + x % XB) * (int)TS);
+    return (uint32_t)((((y * nxb + x / XB) * QS) * XB + x % XB) * (int)TS);
   };
   uint32_t ioxy[9], hoxy[9];
   uint32_t soff;  // store offset: own node, or the trash area for ragged-tile lanes
@@ -318,7 +320,7 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
             node_off(cx > 0 ? xm : (cx < 0 ? xp : gx), cy > 0 ? ym : (cy < 0 ? yp : gy));
     ilds = (ly + HY) * W2 + (lx + 1);
     own = gy * nx + gx;
-    soff = ivalid ? ioxy[4] : zdata + (uint32_t)((((t / XB) * Q) * XB + t % XB) * (int)TS);
+    soff = ivalid ? ioxy[4] : zdata + (uint32_t)((((t / XB) * QS) * XB + t % XB) * (int)TS);
   }
   {
     // halo node h = t of the ring around the tile; lanes t >= H of the halo
@@ -377,12 +379,12 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
-      const char* b = (cz > 0 ? bm : (cz < 0 ? bp : b0)) + i * 128;
+      const char* b = (cz > 0 ? bm : (cz < 0 ? bp : b0)) + i * QB;
       const uint32_t off = oxy[(cx + 1) + 3 * (cy + 1)];
       if (WALLS && cz != 0) {
         const bool bounce = cz > 0 ? lo : hi;
         const int o = L::opp[i];
-        const C v = St::dec(gld<T>(bounce ? b0 + o * 128 : b, bounce ? oxy[4] : off), (C)0);
+        const C v = St::dec(gld<T>(bounce ? b0 + o * QB : b, bounce ? oxy[4] : off), (C)0);
         f[i] = v + (bounce ? shift[o] : shift[i]);
         if (!St::shifted) f[i] = v;
       } else {
@@ -480,7 +482,7 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
       collide<L, C, COLL>(f, dp, rho, u, F, omega, rate, fs);
       char* dz = dst + (uint64_t)z * zblock;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) gst<T>(dz + i * 128, soff, St::enc(fs[i], shift[i]));
+      for (int i = 0; i < Q; ++i) gst<T>(dz + i * QB, soff, St::enc(fs[i], shift[i]));
     } else if (MODE == MODE_MOMENTS) {
       if (ivalid) {
         out_rho[nid] = (double)rho;
