@@ -250,13 +250,20 @@ int plbm_reduce(plbm_lattice* lat, plbm_diag* out);
 /* Release the handle (not the caller's device memory). */
 void plbm_destroy(plbm_lattice* lat);
 
-/* Continuous batching of lattices that share a lattice kind, collision,
- * storage and boundary kinds ("type").  max_slots bounds the number attached
- * at once.  The batch owns no lattice memory; its slot table lives in a
- * caller-owned device buffer of plbm_batch_bytes(max_slots, max_tiles) bytes.
- * Each plbm_batch_step(n) enqueues n steps of every attached lattice as one
- * launch per step covering all slots; attach/detach rewrite the device slot
- * table only.  Results are bitwise identical to stepping each lattice alone. */
+/* Continuous batching.  Attached lattices may differ in size, lattice kind,
+ * collision, storage and walls; those that share all four ("a type") are
+ * advanced by one launch per step whose workgroups cover the tiles of every
+ * such slot, so each step costs one launch per type present.  max_slots
+ * bounds the lattices attached at once and max_tiles their tiles together.
+ * The batch owns no lattice memory; its work table lives in a caller-owned
+ * device buffer of plbm_batch_bytes(max_slots, max_tiles) bytes and is
+ * rewritten on the first step after an attach or detach.  plbm_batch_step(n)
+ * enqueues n steps of every attached lattice on the batch's stream (pairs of
+ * steps replayed from a captured HIP graph).  Attached lattices must not be
+ * stepped through their own handles meanwhile.  Results are bitwise identical
+ * to stepping each lattice alone.
+ * Errors: PLBM_E_INVALID (bad slot, lattice already attached),
+ * PLBM_E_NOMEM (dev_bytes too small, no free slot, more than max_tiles tiles). */
 int plbm_batch_bytes(int32_t max_slots, int64_t max_tiles, uint64_t* bytes);
 int plbm_batch_create(int32_t max_slots, int64_t max_tiles, void* dev_mem, uint64_t dev_bytes, void* hip_stream,
                       plbm_batch** out);
