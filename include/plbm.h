@@ -67,6 +67,16 @@ extern "C" {
 #define PLBM_F32 1   /* float32 storage and arithmetic; psi(rho) evaluated in float64 */
 #define PLBM_F16S 2  /* IEEE half storing f_i - w_i rho0; float32 arithmetic; float64 psi */
 #define PLBM_BF16S 3 /* bfloat16 storing f_i - w_i rho0; float32 arithmetic; float64 psi */
+/* Locally shifted 16-bit storage: f_i - w_i rho_ref(x), with rho_ref(x) a
+ * per-node reference density (the node's density at the previous step,
+ * rounded to half precision, kept in an extra 2-byte-per-node A-B array and
+ * counted by plbm_lattice_bytes).  Every population is encoded with the
+ * reference of the node that decodes it, so the reference's own rounding
+ * costs nothing; the stored deviation is the non-equilibrium and velocity
+ * part only, which keeps vapour and liquid at the same relative precision.
+ * Extra traffic: 4 bytes per node update.  float32 arithmetic, float64 psi. */
+#define PLBM_F16R 4
+#define PLBM_BF16R 5
 /* boundary kinds, per axis */
 #define PLBM_PERIODIC 0
 #define PLBM_HALFWAY_BB 1 /* walls half a spacing outside the first and last node */
@@ -124,7 +134,7 @@ typedef struct plbm_lattice_params {
 typedef struct plbm_lattice_desc {
   int32_t lattice;   /* PLBM_D2Q9 | PLBM_D3Q19 */
   int32_t collision; /* PLBM_BGK | PLBM_MRT */
-  int32_t storage;   /* PLBM_F64 | PLBM_F32 | PLBM_F16S | PLBM_BF16S */
+  int32_t storage;   /* PLBM_F64 | PLBM_F32 | PLBM_F16S | PLBM_BF16S | PLBM_F16R | PLBM_BF16R */
   int32_t nx, ny, nz; /* nodes per axis; D2Q9 uses nx, ny and requires nz = 1 */
   int32_t bc[3];      /* per axis x, y, z: PLBM_PERIODIC or PLBM_HALFWAY_BB.
                          Walls are supported on the last axis only (z in 3-D,
@@ -236,7 +246,10 @@ int plbm_moments_device(plbm_lattice* lat, void* rho_dev, void* u_dev);
 int plbm_read_populations(plbm_lattice* lat, double* f);
 
 /* Replace the state by host float64 populations f[q][...] (checkpoint
- * restore, fault injection).  Time is left unchanged.  Synchronises. */
+ * restore, fault injection).  Time is left unchanged.  Synchronises.
+ * Locally shifted storage takes its reference densities from these
+ * populations (two passes over f), so a read-write round trip is exact to
+ * the storage rounding but not bitwise. */
 int plbm_write_populations(plbm_lattice* lat, const double* f);
 
 /* Steps taken since the last initialisation. */

@@ -32,6 +32,8 @@ SOURCES = {
     "plbm_k_f32.hip": [],
     "plbm_k_f16s.hip": [],
     "plbm_k_bf16s.hip": [],
+    "plbm_k_f16r.hip": [],
+    "plbm_k_bf16r.hip": [],
     "plbm_api.hip": [],
     "plbm_params.cpp": ["-x", "hip", "-ffp-contract=off"],
 }

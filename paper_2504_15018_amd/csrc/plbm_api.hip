@@ -53,8 +53,10 @@ struct Layout {
   uint64_t zdata;  // bytes of node data of one z plane of stored populations
   uint64_t zblock; // zdata plus a trash area for the ragged-tile lanes of one workgroup
   int64_t N;
-  uint64_t popA, popB, aux, uprev, red, kp, total;
+  uint64_t popA, popB, refA, refB, aux, uprev, red, kp, total;
 };
+
+bool local_shift(int storage) { return storage == PLBM_F16R || storage == PLBM_BF16R; }
 
 int choose_cz(int nzk, int tiles_xy) {
   if (const char* e = std::getenv("PLBM_CZ")) {
@@ -75,7 +77,7 @@ int make_layout(const plbm_lattice_desc* d, Layout* L) {
   if (!d) return set_error(PLBM_E_INVALID, "null descriptor");
   if (d->lattice != PLBM_D2Q9 && d->lattice != PLBM_D3Q19) return set_error(PLBM_E_INVALID, "unknown lattice kind");
   if (d->collision != PLBM_BGK && d->collision != PLBM_MRT) return set_error(PLBM_E_INVALID, "unknown collision");
-  if (d->storage < PLBM_F64 || d->storage > PLBM_BF16S) return set_error(PLBM_E_INVALID, "unknown storage");
+  if (d->storage < PLBM_F64 || d->storage > PLBM_BF16R) return set_error(PLBM_E_INVALID, "unknown storage");
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) return set_error(PLBM_E_INVALID, "lattice sizes must be >= 1");
   const bool is2d = d->lattice == PLBM_D2Q9;
   if (is2d && d->nz != 1) return set_error(PLBM_E_INVALID, "D2Q9 requires nz = 1");
@@ -117,6 +119,12 @@ int make_layout(const plbm_lattice_desc* d, Layout* L) {
   off = align_up(off + L->zblock * L->nzk);
   L->popB = off;
   off = align_up(off + L->zblock * L->nzk);
+  // reference densities of locally shifted storage: N nodes + a trash slot per thread
+  const uint64_t nref = local_shift(d->storage) ? (uint64_t)(L->N + 256) * 2 : 0;
+  L->refA = off;
+  off = align_up(off + nref);
+  L->refB = off;
+  off = align_up(off + nref);
   L->aux = off;
   off = align_up(off + 4ull * L->N * 8);
   L->uprev = off;
@@ -153,7 +161,9 @@ hipError_t launch_step(const plbm_lattice_desc& d, StepLaunch& a) {
     case PLBM_F64: return launch_step_f64(a);
     case PLBM_F32: return launch_step_f32(a);
     case PLBM_F16S: return launch_step_f16s(a);
-    default: return launch_step_bf16s(a);
+    case PLBM_BF16S: return launch_step_bf16s(a);
+    case PLBM_F16R: return launch_step_f16r(a);
+    default: return launch_step_bf16r(a);
   }
 }
 
@@ -162,7 +172,9 @@ hipError_t launch_aux(const plbm_lattice_desc& d, AuxLaunch& a) {
     case PLBM_F64: return launch_aux_f64(a);
     case PLBM_F32: return launch_aux_f32(a);
     case PLBM_F16S: return launch_aux_f16s(a);
-    default: return launch_aux_bf16s(a);
+    case PLBM_BF16S: return launch_aux_bf16s(a);
+    case PLBM_F16R: return launch_aux_f16r(a);
+    default: return launch_aux_bf16r(a);
   }
 }
 
@@ -216,6 +228,8 @@ void fill_kparams(plbm_lattice* L) {
   std::memset(&k, 0, sizeof(k));
   k.pop[0] = L->mem + y.popA;
   k.pop[1] = L->mem + y.popB;
+  k.ref[0] = local_shift(L->desc.storage) ? L->mem + y.refA : nullptr;
+  k.ref[1] = local_shift(L->desc.storage) ? L->mem + y.refB : nullptr;
   k.aux = reinterpret_cast<double*>(L->mem + y.aux);
   k.uprev = reinterpret_cast<float*>(L->mem + y.uprev);
   k.red = reinterpret_cast<double*>(L->mem + y.red);
@@ -449,6 +463,15 @@ int plbm_write_populations(plbm_lattice* L, const double* f) {
   if (!f) return set_error(PLBM_E_INVALID, "null input");
   const int64_t N = L->lay.N;
   double* aux = aux_ptr(L);
+  if (local_shift(L->desc.storage)) {
+    // reference densities first: rho = sum_q f_q, then half precision
+    for (int q = 0; q < L->lay.Q; ++q) {
+      HIPCHK(hipMemcpyAsync(aux, f + (size_t)q * N, N * 8, hipMemcpyHostToDevice, L->stream));
+      HIPCHK(launch_accum(L->stream, aux_blocks(N), N, q == 0, aux, aux + N));
+      HIPCHK(hipStreamSynchronize(L->stream));
+    }
+    HIPCHK(launch_set_ref(L->stream, aux_blocks(N), L->kp_dev, (int)(L->t & 1), aux + N));
+  }
   for (int q = 0; q < L->lay.Q; ++q) {
     HIPCHK(hipMemcpyAsync(aux, f + (size_t)q * N, N * 8, hipMemcpyHostToDevice, L->stream));
     int st = run_aux(L, AUX_WRITE_POP, q, aux, nullptr, nullptr, nullptr);

@@ -47,14 +47,24 @@ __device__ __forceinline__ double feq64(int i, double rho, const double* u) {
   return L::w[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
 }
 
+// Density whose multiples w_i rho shift the stored populations of node n:
+// the global rho0, or the node's reference density (locally shifted storage).
+template <class St>
+__device__ __forceinline__ double shift_density(const KParams& p, int par, int64_t n) {
+  if constexpr (St::local) return (double)reinterpret_cast<const RefT*>(p.ref[par])[n];
+  else return p.rho0_shift;
+}
+
 template <class L, class St>
-__device__ __forceinline__ void write_equilibrium(const KParams& p, int par, int x, int y, int z, double rho,
-                                                  const double* u) {
+__device__ __forceinline__ void write_equilibrium(const KParams& p, int par, int64_t n, int x, int y, int z,
+                                                  double rho, const double* u) {
   typename St::T* A = reinterpret_cast<typename St::T*>(p.pop[par]);
+  if constexpr (St::local) reinterpret_cast<RefT*>(p.ref[par])[n] = (RefT)(float)rho;
+  const double rs = shift_density<St>(p, par, n);
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     const int dir = storage_dir<L>(p, i, z);
-    A[storage_index<L, typename St::T>(p, i, x, y, z)] = St::enc64(feq64<L>(i, rho, u), L::w[dir] * p.rho0_shift);
+    A[storage_index<L, typename St::T>(p, i, x, y, z)] = St::enc64(feq64<L>(i, rho, u), L::w[dir] * rs);
   }
 }
 
@@ -76,7 +86,7 @@ __global__ __launch_bounds__(256) void k_init_fields(const KParams* __restrict__
     double uu[3] = {0.0, 0.0, 0.0};
     if (u != nullptr)
       for (int a = 0; a < L::D; ++a) uu[a] = u[(size_t)a * (size_t)p.N + n];
-    write_equilibrium<L, St>(p, par, x, y, z, rho[n], uu);
+    write_equilibrium<L, St>(p, par, n, x, y, z, rho[n], uu);
   }
 }
 
@@ -111,7 +121,7 @@ __global__ __launch_bounds__(256) void k_init_shape(const KParams* __restrict__ 
     } else {  // layers: liquid below `level` along `axis`
       rho = 0.5 * (sh.rho_in + sh.rho_out) - 0.5 * dl * tanh(2.0 * (pc[sh.axis] - sh.level) / sh.W);
     }
-    write_equilibrium<L, St>(p, par, x, y, z, rho, sh.u0);
+    write_equilibrium<L, St>(p, par, n, x, y, z, rho, sh.u0);
   }
 }
 
@@ -125,7 +135,7 @@ __global__ __launch_bounds__(256) void k_read_pop(const KParams* __restrict__ P,
     int x, y, z;
     node_xyz(p, n, &x, &y, &z);
     const int dir = storage_dir<L>(p, dirq, z);
-    out[n] = St::dec64(A[storage_index<L, typename St::T>(p, dirq, x, y, z)], L::w[dir] * p.rho0_shift);
+    out[n] = St::dec64(A[storage_index<L, typename St::T>(p, dirq, x, y, z)], L::w[dir] * shift_density<St>(p, par, n));
   }
 }
 
@@ -139,7 +149,7 @@ __global__ __launch_bounds__(256) void k_write_pop(const KParams* __restrict__ P
     int x, y, z;
     node_xyz(p, n, &x, &y, &z);
     const int dir = storage_dir<L>(p, dirq, z);
-    A[storage_index<L, typename St::T>(p, dirq, x, y, z)] = St::enc64(in[n], L::w[dir] * p.rho0_shift);
+    A[storage_index<L, typename St::T>(p, dirq, x, y, z)] = St::enc64(in[n], L::w[dir] * shift_density<St>(p, par, n));
   }
 }
 

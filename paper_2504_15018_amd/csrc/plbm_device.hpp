@@ -115,7 +115,12 @@ struct MrtInvNorm {
 // ---------------------------------------------------------------------------
 // Storage codecs.  Shifted storage keeps f_i - w_i rho0 (one global rho0) so
 // that half-precision formats spend their bits on the deviation from the
-// reference state.
+// reference state.  Locally shifted storage (local = true) keeps
+// f_i - w_i rho_ref(x) instead, with rho_ref(x) a per-node reference density
+// held in its own 16-bit array: the node's density at the previous step,
+// rounded to half precision.  The population f_i(x) is encoded with the
+// reference of the node x that will decode it, so encoder and decoder always
+// use the same value and its precision does not matter.
 
 // dec/enc work in the arithmetic type C; dec64/enc64 are the float64 forms
 // used by initialisation and population I/O.
@@ -123,6 +128,7 @@ struct StF64 {
   using T = double;
   using C = double;  // arithmetic type
   static constexpr bool shifted = false;
+  static constexpr bool local = false;
   static __device__ __forceinline__ C dec(T v, C) { return v; }
   static __device__ __forceinline__ T enc(C f, C) { return f; }
   static __device__ __forceinline__ double dec64(T v, double) { return v; }
@@ -133,6 +139,7 @@ struct StF32 {
   using T = float;
   using C = float;
   static constexpr bool shifted = false;
+  static constexpr bool local = false;
   static __device__ __forceinline__ C dec(T v, C) { return v; }
   static __device__ __forceinline__ T enc(C f, C) { return f; }
   static __device__ __forceinline__ double dec64(T v, double) { return (double)v; }
@@ -143,16 +150,25 @@ struct StF16S {
   using T = _Float16;
   using C = float;
   static constexpr bool shifted = true;
+  static constexpr bool local = false;
   static __device__ __forceinline__ C dec(T v, C shift) { return (float)v + shift; }
   static __device__ __forceinline__ T enc(C f, C shift) { return (_Float16)(f - shift); }  // RNE
-  static __device__ __forceinline__ double dec64(T v, double shift) { return (double)(float)v + shift; }
-  static __device__ __forceinline__ T enc64(double f, double shift) { return (_Float16)(float)(f - shift); }
+  // float64 forms: plain operation order, no fused multiply-add with the shift
+  static __device__ __forceinline__ double dec64(T v, double shift) {
+#pragma clang fp contract(off)
+    return (double)(float)v + shift;
+  }
+  static __device__ __forceinline__ T enc64(double f, double shift) {
+#pragma clang fp contract(off)
+    return (_Float16)(float)(f - shift);
+  }
 };
 
 struct StBF16S {
   using T = uint16_t;  // bfloat16 bit pattern
   using C = float;
   static constexpr bool shifted = true;
+  static constexpr bool local = false;
   static __device__ __forceinline__ C dec(T v, C shift) {
     return __uint_as_float(((uint32_t)v) << 16) + shift;
   }
@@ -164,10 +180,25 @@ struct StBF16S {
     return (uint16_t)(u >> 16);
   }
   static __device__ __forceinline__ double dec64(T v, double shift) {
+#pragma clang fp contract(off)
     return (double)__uint_as_float(((uint32_t)v) << 16) + shift;
   }
-  static __device__ __forceinline__ T enc64(double f, double shift) { return enc((float)(f - shift), 0.0f); }
+  static __device__ __forceinline__ T enc64(double f, double shift) {
+#pragma clang fp contract(off)
+    return enc((float)(f - shift), 0.0f);
+  }
 };
+
+struct StF16R : StF16S {
+  static constexpr bool local = true;
+};
+
+struct StBF16R : StBF16S {
+  static constexpr bool local = true;
+};
+
+// Reference density code of locally shifted storage: IEEE half bits.
+using RefT = _Float16;
 
 // ---------------------------------------------------------------------------
 // Kernel parameter block: one per lattice, resident in device memory (the
@@ -177,6 +208,7 @@ enum : int32_t { EOS_PAPER = 0, EOS_PR = 1 };
 
 struct KParams {
   void* pop[2];       // A-B population arrays, each Q*N entries
+  void* ref[2];       // locally shifted storage: A-B reference densities, N + 256 half values
   double* aux;        // float64 staging, 4*N
   float* uprev;       // previous velocity for the residual, D*N
   double* red;        // reduction partials

@@ -5,26 +5,67 @@
 
 namespace plbm {
 
-// Sum the per-tile reduction records of one lattice in tile order (one
-// thread: deterministic, independent of the launch configuration).
-__global__ void k_reduce_final(const KParams* __restrict__ P, int ntiles, RedRec* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const RedRec* r = reinterpret_cast<const RedRec*>(P->red);
-  RedRec o = r[0];
-  for (int k = 1; k < ntiles; ++k) {
-    neumaier_add(o.mass_s, o.mass_c, r[k].mass_s);
-    o.mass_c += r[k].mass_c;
-    for (int a = 0; a < 3; ++a) o.mom[a] += r[k].mom[a];
-    o.max_u = fmax(o.max_u, r[k].max_u);
-    o.max_du = fmax(o.max_du, r[k].max_du);
-    o.flags = (double)((int)o.flags | (int)r[k].flags);
-  }
-  *out = o;
+// Combine the per-tile reduction records of one lattice: thread k folds
+// tiles k, k + 256, ... in order, then a fixed pairwise tree in LDS.  The
+// order depends only on the tile count, so the result is deterministic.
+__device__ __forceinline__ void red_combine(RedRec& o, const RedRec& q) {
+  neumaier_add(o.mass_s, o.mass_c, q.mass_s);
+  o.mass_c += q.mass_c;
+  for (int a = 0; a < 3; ++a) o.mom[a] += q.mom[a];
+  o.max_u = fmax(o.max_u, q.max_u);
+  o.max_du = fmax(o.max_du, q.max_du);
+  o.flags = (double)((int)o.flags | (int)q.flags);
 }
 
+__global__ __launch_bounds__(256) void k_reduce_final(const KParams* __restrict__ P, int ntiles,
+                                                      RedRec* __restrict__ out) {
+  __shared__ RedRec sh[256];
+  const int t = threadIdx.x;
+  const RedRec* r = reinterpret_cast<const RedRec*>(P->red);
+  RedRec o;
+  o.mass_s = o.mass_c = 0.0;
+  o.mom[0] = o.mom[1] = o.mom[2] = 0.0;
+  o.max_u = o.max_du = 0.0;
+  o.flags = 0.0;
+  for (int k = t; k < ntiles; k += 256) red_combine(o, r[k]);
+  sh[t] = o;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red_combine(sh[t], sh[t + w]);
+    __syncthreads();
+  }
+  if (t == 0) *out = sh[0];
+}
 
 hipError_t launch_reduce_final(hipStream_t st, const KParams* P, int ntiles, void* out) {
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, st, P, ntiles, reinterpret_cast<RedRec*>(out));
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, P, ntiles, reinterpret_cast<RedRec*>(out));
   return hipGetLastError();
 }
+
+// Locally shifted storage, before k_write_pop: acc[n] (+)= in[n] over the
+// directions (first = 1 starts the sum), then the reference densities
+// ref[n] = acc[n] rounded to float32, then to half precision.
+__global__ __launch_bounds__(256) void k_accum(int64_t N, int first, const double* __restrict__ in,
+                                               double* __restrict__ acc) {
+  for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x)
+    acc[n] = (first ? 0.0 : acc[n]) + in[n];
+}
+
+__global__ __launch_bounds__(256) void k_set_ref(const KParams* __restrict__ P, int par, const double* __restrict__ acc) {
+  const KParams p = *P;
+  RefT* ref = reinterpret_cast<RefT*>(p.ref[par]);
+  for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < p.N; n += (int64_t)gridDim.x * blockDim.x)
+    ref[n] = (RefT)(float)acc[n];
+}
+
+hipError_t launch_accum(hipStream_t st, int nblocks, int64_t N, int first, const double* in, double* acc) {
+  hipLaunchKernelGGL(k_accum, dim3(nblocks), dim3(256), 0, st, N, first, in, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_ref(hipStream_t st, int nblocks, const KParams* P, int par, const double* acc) {
+  hipLaunchKernelGGL(k_set_ref, dim3(nblocks), dim3(256), 0, st, P, par, acc);
+  return hipGetLastError();
+}
+
 }  // namespace plbm

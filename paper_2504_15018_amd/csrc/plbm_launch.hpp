@@ -68,6 +68,12 @@ hipError_t launch_aux_f64(const AuxLaunch&);
 hipError_t launch_aux_f32(const AuxLaunch&);
 hipError_t launch_aux_f16s(const AuxLaunch&);
 hipError_t launch_aux_bf16s(const AuxLaunch&);
+hipError_t launch_step_f16r(const StepLaunch&);
+hipError_t launch_step_bf16r(const StepLaunch&);
+hipError_t launch_aux_f16r(const AuxLaunch&);
+hipError_t launch_aux_bf16r(const AuxLaunch&);
+hipError_t launch_accum(hipStream_t st, int nblocks, int64_t N, int first, const double* in, double* acc);
+hipError_t launch_set_ref(hipStream_t st, int nblocks, const KParams* P, int par, const double* acc);
 hipError_t launch_reduce_final(hipStream_t st, const KParams* P, int ntiles, void* out);
 
 }  // namespace plbm

@@ -14,6 +14,8 @@
 // two extra planes per chunk are re-read from L2 / the Infinity Cache.
 #pragma once
 
+#include <type_traits>
+
 #include "plbm_device.hpp"
 
 namespace plbm {
@@ -253,8 +255,15 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   constexpr int XB = Lines<T>::XB;
   constexpr int QB = Lines<T>::QB;
   constexpr int QS = Lines<T>::template slots<Q>();
+  // 16-bit storage: populations stay in their stored form in registers until
+  // they are used, so that the loads of a plane overlap the collision of the
+  // previous one; they are decoded where they are summed and collided.
+  constexpr bool RAW = St::shifted;
+  constexpr bool LOC = St::local;  // per-node reference densities
+  using R = typename std::conditional<RAW, T, C>::type;
 
   __shared__ C lds_psi[4 * PL + 64];  // 4-plane psi ring + a slot per lane for idle halo lanes
+  __shared__ C lds_ref[LOC ? 4 * PL + 64 : 1];  // reference densities, same ring
   __shared__ RedRec red_lds[(MODE == MODE_REDUCE) ? NT : 1];
 
   int wid = xcd_remap(blockIdx.x, gridDim.x);
@@ -302,7 +311,7 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   };
   uint32_t ioxy[9], hoxy[9];
   uint32_t soff;  // store offset: own node, or the trash area for ragged-tile lanes
-  int ilds, hlds, own;
+  int ilds, hlds, own, hown;
   bool ivalid;
   {
     const int lx = t % TX, ly = t / TX;
@@ -356,10 +365,12 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
           hoxy[(cx + 1) + 3 * (cy + 1)] =
               node_off(cx > 0 ? xm : (cx < 0 ? xp : gx), cy > 0 ? ym : (cy < 0 ? yp : gy));
       hlds = (ly + HY) * W2 + (lx + 1);
+      hown = gy * nx + gx;
     } else {
 #pragma unroll
       for (int c = 0; c < 9; ++c) hoxy[c] = ioxy[c];
       hlds = 4 * PL + (t & 63);
+      hown = own;
     }
   }
 
@@ -375,7 +386,9 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   // marching axis, a population whose source lies beyond the wall is the
   // opposite population of the same node (half-way bounce-back); the choice
   // is wave-uniform and made by selects, keeping the loop free of branches.
-  auto pull = [&](const uint32_t* oxy, const char* bm, const char* b0, const char* bp, bool lo, bool hi, C* f) {
+  // A bounced population is decoded with its own shift: opposite directions
+  // have equal weights.
+  auto pull = [&](const uint32_t* oxy, const char* bm, const char* b0, const char* bp, bool lo, bool hi, R* f) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
@@ -384,21 +397,26 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
       if (WALLS && cz != 0) {
         const bool bounce = cz > 0 ? lo : hi;
         const int o = L::opp[i];
-        const C v = St::dec(gld<T>(bounce ? b0 + o * QB : b, bounce ? oxy[4] : off), (C)0);
-        f[i] = v + (bounce ? shift[o] : shift[i]);
-        if (!St::shifted) f[i] = v;
+        f[i] = (R)gld<T>(bounce ? b0 + o * QB : b, bounce ? oxy[4] : off);
       } else {
-        f[i] = St::dec(gld<T>(b, off), shift[i]);
+        f[i] = (R)gld<T>(b, off);
       }
     }
   };
+  // decoded population i of a node whose reference density is ref (LOC)
+  auto decode = [&](const R* f, int i, C ref) -> C {
+    if constexpr (RAW) return St::dec(f[i], LOC ? (C)L::w[i] * ref : shift[i]);
+    else return f[i];
+  };
 
-  auto density = [&](const C* f) {
-    C r = f[0];
+  auto density = [&](const R* f, C ref) {
+    C r = decode(f, 0, ref);
 #pragma unroll
-    for (int i = 1; i < Q; ++i) r += f[i];
+    for (int i = 1; i < Q; ++i) r += decode(f, i, ref);
     return r;
   };
+  const RefT* const ref_src = LOC ? reinterpret_cast<const RefT*>(kp->ref[par]) : nullptr;
+  RefT* const ref_dst = LOC ? reinterpret_cast<RefT*>(kp->ref[par ^ 1]) : nullptr;
 
   bool psi_neg = false;
 
@@ -406,7 +424,7 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   // previous plane is collided: issue() pulls the populations of logical
   // plane zl (tile node into fo, halo node into ho); finish() sums rho and
   // writes psi of the tile and the halo ring into the LDS ring.
-  auto issue = [&](auto halo_c, int zl, C* fo, C* ho) {
+  auto issue = [&](auto halo_c, int zl, R* fo, R* ho, RefT& qo, RefT& qh) {
     constexpr bool HALO = decltype(halo_c)::value;
     const int pz = wrapz(zl);
     const int zm = pz == 0 ? (WALLS ? 0 : nz - 1) : pz - 1;
@@ -418,20 +436,31 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     const bool hi = WALLS && pz == nz - 1;
     pull(ioxy, bm, b0, bp, lo, hi, fo);
     if constexpr (HALO) pull(hoxy, bm, b0, bp, lo, hi, ho);
+    if constexpr (LOC) {
+      qo = ref_src[(uint32_t)(pz * plane + own)];
+      if constexpr (HALO) qh = ref_src[(uint32_t)(pz * plane + hown)];
+    }
   };
-  auto finish = [&](auto halo_c, int zl, bool keep, const C* fo, C& ro, const C* ho) {
+  auto as_ref = [&](RefT v) -> C {
+    if constexpr (LOC) return (C)v;
+    else return (C)0;
+  };
+  auto finish = [&](auto halo_c, int zl, bool keep, const R* fo, C& ro, RefT qo, const R* ho, RefT qh) {
     constexpr bool HALO = decltype(halo_c)::value;
     C* sl = lds_psi + ((zl - z0 + 1) & 3) * PL;
-    const C r = density(fo);
+    const C r = density(fo, as_ref(qo));
     ro = r;
     bool ng;
     sl[ilds] = psi_eval<C>(eos, (double)r, &ng);
     psi_neg |= ng && ivalid && keep;
+    if constexpr (LOC) lds_ref[((zl - z0 + 1) & 3) * PL + ilds] = (C)(RefT)r;
     if constexpr (HALO) {
       bool hng;
-      const C ph = psi_eval<C>(eos, (double)density(ho), &hng);
+      const C rh = density(ho, as_ref(qh));
+      const C ph = psi_eval<C>(eos, (double)rh, &hng);
       // the spare slots of idle lanes sit past the ring
       (hlds < 4 * PL ? sl : lds_psi)[hlds] = ph;
+      if constexpr (LOC) (hlds < 4 * PL ? lds_ref + ((zl - z0 + 1) & 3) * PL : lds_ref)[hlds] = (C)(RefT)rh;
     }
   };
 
@@ -454,7 +483,10 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   int acc_flags = 0;
 
   // Phase B for output plane z with the populations f / rho of that plane.
-  auto phaseB = [&](int z, const C* f, C rho) {
+  auto phaseB = [&](int z, const R* fr, C rho, RefT qr) {
+    C f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = decode(fr, i, as_ref(qr));
     const C* s_m = lds_psi + ((z - z0) & 3) * PL;
     const C* s_0 = lds_psi + ((z - z0 + 1) & 3) * PL;
     const C* s_p = lds_psi + ((z - z0 + 2) & 3) * PL;
@@ -481,8 +513,28 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
       C fs[Q];
       collide<L, C, COLL>(f, dp, rho, u, F, omega, rate, fs);
       char* dz = dst + (uint64_t)z * zblock;
+      if constexpr (LOC) {
+        // f*_i(x) is decoded next step by x + c_i (by x itself when it
+        // bounces off a wall), with that node's reference density, which is
+        // its density now, rounded to half precision
+        const C* r_m = lds_ref + ((z - z0) & 3) * PL;
+        const C* r_0 = lds_ref + ((z - z0 + 1) & 3) * PL;
+        const C* r_p = lds_ref + ((z - z0 + 2) & 3) * PL;
+        const bool zlo = WALLS && z == 0, zhi = WALLS && z == nz - 1;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) gst<T>(dz + i * QB, soff, St::enc(fs[i], shift[i]));
+        for (int i = 0; i < Q; ++i) {
+          const int cz = L::cz[i];
+          const C* rr = cz < 0 ? r_m : (cz > 0 ? r_p : r_0);
+          C rd = rr[ilds + L::cx[i] + L::cy[i] * W2];
+          if (WALLS && cz != 0) rd = (cz > 0 ? zhi : zlo) ? r_0[ilds] : rd;
+          gst<T>(dz + i * QB, soff, St::enc(fs[i], (C)L::w[i] * rd));
+        }
+        const uint32_t ridx = ivalid ? nid : (uint32_t)N + (uint32_t)t;
+        ref_dst[ridx] = (RefT)rho;
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) gst<T>(dz + i * QB, soff, St::enc(fs[i], shift[i]));
+      }
     } else if (MODE == MODE_MOMENTS) {
       if (ivalid) {
         out_rho[nid] = (double)rho;
@@ -518,32 +570,33 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   // plane z is collided while plane z+1 waits with its psi in LDS and the
   // loads of plane z+2 are in flight.
   auto march = [&](auto halo_c) {
-    C f0[Q], f1[Q], f2[Q], hb[Q];
-    C r0, r1, r2;
-    issue(halo_c, z0 - 1, f0, hb);
-    finish(halo_c, z0 - 1, false, f0, r0, hb);
-    issue(halo_c, z0, f0, hb);
-    finish(halo_c, z0, true, f0, r0, hb);
-    issue(halo_c, z0 + 1, f1, hb);
-    finish(halo_c, z0 + 1, true, f1, r1, hb);
+    R f0[Q], f1[Q], f2[Q], hb[Q];
+    C r0, r1, r2;      // densities
+    RefT q0 = 0, q1 = 0, q2 = 0, qh = 0;  // reference densities (LOC)
+    issue(halo_c, z0 - 1, f0, hb, q0, qh);
+    finish(halo_c, z0 - 1, false, f0, r0, q0, hb, qh);
+    issue(halo_c, z0, f0, hb, q0, qh);
+    finish(halo_c, z0, true, f0, r0, q0, hb, qh);
+    issue(halo_c, z0 + 1, f1, hb, q1, qh);
+    finish(halo_c, z0 + 1, true, f1, r1, q1, hb, qh);
     // loads of z+2 into pf, barrier, collide z, psi of z+2
-    auto stepz = [&](int z, C* cur, C rc, C* pf, C& rp) {
-      issue(halo_c, z + 2, pf, hb);
+    auto stepz = [&](int z, R* cur, C rc, RefT qc, R* pf, C& rp, RefT& qp) {
+      issue(halo_c, z + 2, pf, hb, qp, qh);
       __syncthreads();
-      phaseB(z, cur, rc);
-      finish(halo_c, z + 2, true, pf, rp, hb);
+      phaseB(z, cur, rc, qc);
+      finish(halo_c, z + 2, true, pf, rp, qp, hb, qh);
     };
     int z = z0;
     for (; z + 2 < z1; z += 3) {
-      stepz(z, f0, r0, f2, r2);
-      stepz(z + 1, f1, r1, f0, r0);
-      stepz(z + 2, f2, r2, f1, r1);
+      stepz(z, f0, r0, q0, f2, r2, q2);
+      stepz(z + 1, f1, r1, q1, f0, r0, q0);
+      stepz(z + 2, f2, r2, q2, f1, r1, q1);
     }
     if (z < z1) {
-      stepz(z, f0, r0, f2, r2);
+      stepz(z, f0, r0, q0, f2, r2, q2);
       ++z;
     }
-    if (z < z1) stepz(z, f1, r1, f0, r0);
+    if (z < z1) stepz(z, f1, r1, q1, f0, r0, q0);
   };
   if (wave < HW)
     march(BoolC<true>{});

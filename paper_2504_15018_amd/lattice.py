@@ -10,7 +10,8 @@ from . import native as N
 
 LATTICE = {"D2Q9": N.PLBM_D2Q9, "D3Q19": N.PLBM_D3Q19}
 COLLISION = {"bgk": N.PLBM_BGK, "mrt": N.PLBM_MRT}
-STORAGE = {"f64": N.PLBM_F64, "f32": N.PLBM_F32, "f16s": N.PLBM_F16S, "bf16s": N.PLBM_BF16S}
+STORAGE = {"f64": N.PLBM_F64, "f32": N.PLBM_F32, "f16s": N.PLBM_F16S, "bf16s": N.PLBM_BF16S,
+           "f16r": N.PLBM_F16R, "bf16r": N.PLBM_BF16R}
 Q_OF = {"D2Q9": 9, "D3Q19": 19}
 
 

@@ -23,7 +23,7 @@ PLBM_E_UNSTABLE = -5
 PLBM_E_NOCONVERGE = -6
 PLBM_D2Q9, PLBM_D3Q19 = 0, 1
 PLBM_BGK, PLBM_MRT = 0, 1
-PLBM_F64, PLBM_F32, PLBM_F16S, PLBM_BF16S = 0, 1, 2, 3
+PLBM_F64, PLBM_F32, PLBM_F16S, PLBM_BF16S, PLBM_F16R, PLBM_BF16R = 0, 1, 2, 3, 4, 5
 PLBM_PERIODIC, PLBM_HALFWAY_BB = 0, 1
 PLBM_EOS_PAPER, PLBM_EOS_PENG_ROBINSON = 0, 1
 PLBM_FLAG_NAN, PLBM_FLAG_RHO_NONPOS, PLBM_FLAG_PSI_NEG = 1, 2, 4
