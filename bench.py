@@ -30,6 +30,30 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 REDUCE_EVERY = 100
+PROFILE = os.path.join(ROOT, "profiles", "k_step_d3q19_256cubed_mrt_f32.json")
+KERNEL_SOURCES = ["plbm_device.hpp", "plbm_step.hpp", "plbm_launch.hpp", "plbm_kernels_inst.hpp", "plbm_k_f32.hip"]
+
+
+def kernel_source_hash():
+    """sha256 over the sources of the float32 step kernel (identifies the kernel a profile was taken of)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2504_15018_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(storage, collision, size):
+    """HBM bytes per update launch from the committed rocprofv3 counters, if they were taken of this kernel
+    and workload; else None."""
+    if (storage, collision, size) != ("f32", "mrt", 256) or not os.path.exists(PROFILE):
+        return None
+    with open(PROFILE) as fh:
+        prof = json.load(fh)
+    if prof.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return prof["traffic_bytes"]
 
 
 def log(msg):
@@ -92,6 +116,82 @@ def copy_probe(torch, nbytes=2 << 30, reps=20):
                       "copy_GBps_read_plus_write": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
 
 
+def precision_run(torch, N, Lattice, steps):
+    """Layered channel between plates, 384 x 384 x 128 (walls on z, F_g = 1e-6 x, BGK tau = 1), in every
+    storage format; coexistence densities and the u_x profile against the float64 run."""
+    dims = (384, 384, 128)
+    prm = N.plbm_params_pr_lattice(0.8, 0.326, 2.0, 1.0, 1.0, 1.0, body_force=(1e-6, 0.0, 0.0))
+    rows = {}
+    cols = {}
+    for st in ["f64", "f32", "f16s", "bf16s", "f16r", "bf16r"]:
+        lat = Lattice("D3Q19", dims, prm, collision="bgk", storage=st, walls=True)
+        lat.init_shape(N.PLBM_SHAPE_LAYERS, prm.rho_l, prm.rho_v, W=5.0, level=64.0, axis=2)
+        rho = torch.empty(lat.N, dtype=torch.float64, device="cuda")
+        u = torch.empty(3 * lat.N, dtype=torch.float64, device="cuda")
+        lat.step(20)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        lat.step(steps - 20)
+        e1.record(lat.stream)
+        lat.stream.synchronize()
+        ms = e0.elapsed_time(e1) / (steps - 20)
+        N.plbm_moments_device(lat.h, rho.data_ptr(), u.data_ptr())
+        lat.stream.synchronize()
+        r = rho.view(128, 384, 384)
+        ux = u.view(3, 128, 384, 384)[0]
+        uniform = bool((r == r[:, :1, :1]).all()) and bool((ux == ux[:, :1, :1]).all())
+        cols[st] = (r[:, 0, 0].cpu().numpy(), ux[:, 0, 0].cpu().numpy())
+        d = lat.reduce(allow_unstable=True)
+        S = {"f64": 8, "f32": 4}.get(st, 2)
+        extra = 4 if st.endswith("r") else 0  # reference densities read and written
+        rows[st] = {"ms_per_step": round(ms, 4), "MLUPS": round(lat.N / ms / 1e3, 1),
+                    "GBps_algorithmic": round((2 * 19 * S + extra) * lat.N / ms / 1e6, 1),
+                    "laterally_uniform": uniform, "flags": d.flags}
+        log(f"[precision] {st}: {ms:.4f} ms/step, flags {d.flags}")
+        lat.close()
+        del rho, u
+    r64, u64 = cols["f64"]
+    for st in rows:
+        r, uu = cols[st]
+        rows[st]["rho_l_rel_err"] = float(abs(r[32] - r64[32]) / r64[32])
+        rows[st]["rho_v_rel_err"] = float(abs(r[96] - r64[96]) / r64[96])
+        rows[st]["ux_profile_rel_err"] = float(abs(uu - u64).max() / abs(u64).max())
+    return {"workload": f"D3Q19 384x384x128 channel, half-way bounce-back plates on z, F_g = 1e-6 x, layered "
+                        f"liquid below z = 64, PR T/Tc = 0.8, BGK tau = 1, {steps} steps",
+            "rho_v_f64": float(r64[96]), "rho_l_f64": float(r64[32]), "ux_max_f64": float(abs(u64).max()),
+            "storages": rows}
+
+
+def serve_run(N, seconds, budget_gb):
+    """Continuous-batching serving of the Poisson request stream (50 req/s, 500 requests, seed 0): D2Q9 64^2 to
+    1024^2 and D3Q19 64^3 to 192^3 droplets, T/Tc in [0.6, 0.9], radius [0.15, 0.35] of the side, f32, BGK,
+    converged at max|du|/step <= 1e-8 over 100 steps.  Then a second stream at 0.8 x the measured capacity."""
+    import plbm_synth as syn
+    from paper_2504_15018_amd.serving import Server, from_synth
+
+    def one(reqs, label):
+        srv = Server(budget_bytes=int(budget_gb * 1e9), max_slots=64, max_tiles=1 << 21, check_every=100,
+                     tol=1e-8, max_steps=2_000_000)
+        last = [0.0]
+
+        def progress(m):
+            if time.perf_counter() - last[0] > 10:
+                last[0] = time.perf_counter()
+                log(f"[serve:{label}] {m}")
+
+        out = srv.run(reqs, time_limit=seconds, log=progress)
+        srv.close()
+        out.pop("records")
+        return out
+
+    first = one(from_synth(syn.request_stream(500, 50.0, seed=0)), "c5")
+    cap = first["solves_per_s"]
+    rate = max(0.8 * cap, 1e-3)
+    second = one(from_synth(syn.request_stream(max(4, int(rate * seconds * 1.2)), rate, seed=1)), "sustainable")
+    return {"stream": first, "sustainable": dict(second, rate_per_s=rate)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +203,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain device-to-device copy of 2 GiB (HBM reference for the roofline)")
+    ap.add_argument("--precision", action="store_true",
+                    help="storage-format comparison on the 384x384x128 channel instead of the step benchmark")
+    ap.add_argument("--precision-steps", type=int, default=20000)
+    ap.add_argument("--serve", action="store_true", help="serving-loop run instead of the step benchmark")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=240.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the lattice update is not sharded across GPUs here); "
@@ -117,6 +223,14 @@ def main():
         copy_probe(torch)
         return
     N.load()
+    if args.precision:
+        print(json.dumps({"metric": "coexistence density error vs float64 by storage format",
+                          **precision_run(torch, N, Lattice, args.precision_steps)}), flush=True)
+        return
+    if args.serve:
+        print(json.dumps({"metric": "solves/s + p50/p99 time to converged solution",
+                          **serve_run(N, args.serve_seconds, args.serve_budget_gb)}), flush=True)
+        return
     n = args.size
     dims = (n, n, n)
     prm = N.plbm_params_pr_lattice(0.8, 0.326, 2.0, 1.0, 1.0, 1.0)
@@ -169,6 +283,8 @@ def main():
         sys.exit(3)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
+    tb = profiled_traffic(args.storage, args.collision, n)
+    traffic = None if tb is None else round(tb / 1e9, 4)  # GB per update launch
     out = {
         "metric": "MLUPS & % HBM peak (D3Q19 P-LBM step); solves/s + p99 latency at fixed accuracy",
         "value": round(mlups, 2),
@@ -188,7 +304,7 @@ def main():
                    "lattice": "D3Q19", "nodes": nodes, "storage": args.storage, "collision": args.collision,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
