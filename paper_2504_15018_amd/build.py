@@ -27,13 +27,16 @@ COMMON = [
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 SOURCES = {
-    # float64 kernels hold twice the registers: one wave per SIMD avoids spills
-    "plbm_k_f64.hip": ["-ffp-contract=off", "-DPLBM_MIN_WAVES=1"],
+    # Per storage, the kernel shape measured fastest on MI355X (256^3 D3Q19 MRT):
+    # float32 and float64 carry the halo ring on waves of their own (float64
+    # with loads one plane ahead to stay within 256 registers); the 16-bit
+    # formats keep the halo on two of the tile waves.
+    "plbm_k_f64.hip": ["-ffp-contract=off", "-DPLBM_PREFETCH=1"],
     "plbm_k_f32.hip": [],
-    "plbm_k_f16s.hip": [],
-    "plbm_k_bf16s.hip": [],
-    "plbm_k_f16r.hip": [],
-    "plbm_k_bf16r.hip": [],
+    "plbm_k_f16s.hip": ["-DPLBM_HALO_SPLIT=0", "-DPLBM_PREFETCH=1"],
+    "plbm_k_bf16s.hip": ["-DPLBM_HALO_SPLIT=0", "-DPLBM_PREFETCH=1"],
+    "plbm_k_f16r.hip": ["-DPLBM_HALO_SPLIT=0", "-DPLBM_PREFETCH=1"],
+    "plbm_k_bf16r.hip": ["-DPLBM_HALO_SPLIT=0", "-DPLBM_PREFETCH=1"],
     "plbm_api.hip": [],
     "plbm_params.cpp": ["-x", "hip", "-ffp-contract=off"],
 }

@@ -58,22 +58,40 @@ struct Layout {
 
 bool local_shift(int storage) { return storage == PLBM_F16R || storage == PLBM_BF16R; }
 
-int choose_cz(int nzk, int tiles_xy) {
+// Planes per z chunk.  A workgroup spends about cz + 2 plane times on a
+// chunk (the two extra planes of psi are recomputed), and the grid runs in
+// workgroups / resident rounds, where `resident` is how many step workgroups
+// the device holds at once (CUs times the occupancy of the kernel).  A
+// partly filled last round costs about half a round more than its share
+// (measured on the 256^3 cube and the 384x384x128 channel), so the chunk
+// minimises (workgroups / resident + ceil(workgroups / resident)) (cz + 2);
+// on ties the longer chunk.  Without a device (resident <= 0), aim at 512
+// workgroups.
+int choose_cz(int nzk, int tiles_xy, int64_t resident) {
   if (const char* e = std::getenv("PLBM_CZ")) {
     int v = std::atoi(e);
     if (v > 0) return v < nzk ? v : nzk;
   }
-  // about 512 workgroups (two per CU); long chunks amortise the two extra
-  // planes each chunk recomputes
-  int64_t target = 512;
-  int64_t cz = ((int64_t)nzk * tiles_xy + target - 1) / target;
-  if (cz < 4) cz = 4;
-  if (cz > 128) cz = 128;
-  if (cz > nzk) cz = nzk;
-  return (int)cz;
+  if (resident <= 0) {
+    int64_t cz = ((int64_t)nzk * tiles_xy + 511) / 512;
+    if (cz < 4) cz = 4;
+    if (cz > 128) cz = 128;
+    return (int)(cz > nzk ? nzk : cz);
+  }
+  int best = nzk;
+  int64_t best_cost = -1;
+  for (int cz = nzk; cz >= 1 && cz >= (nzk < 4 ? 1 : 4); --cz) {
+    const int64_t wg = (int64_t)tiles_xy * ((nzk + cz - 1) / cz);
+    const int64_t cost = (wg + resident * ((wg + resident - 1) / resident)) * (int64_t)(cz + 2);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = cz;
+    }
+  }
+  return best;
 }
 
-int make_layout(const plbm_lattice_desc* d, Layout* L) {
+int make_layout(const plbm_lattice_desc* d, Layout* L, int64_t resident = 0) {
   if (!d) return set_error(PLBM_E_INVALID, "null descriptor");
   if (d->lattice != PLBM_D2Q9 && d->lattice != PLBM_D3Q19) return set_error(PLBM_E_INVALID, "unknown lattice kind");
   if (d->collision != PLBM_BGK && d->collision != PLBM_MRT) return set_error(PLBM_E_INVALID, "unknown collision");
@@ -98,14 +116,17 @@ int make_layout(const plbm_lattice_desc* d, Layout* L) {
   L->ty = is2d ? TileShape<D2Q9L>::TY : TileShape<D3Q19L>::TY;
   L->tiles_x = (L->nxk + L->tx - 1) / L->tx;
   L->tiles_y = (L->nyk + L->ty - 1) / L->ty;
-  L->cz = choose_cz(L->nzk, L->tiles_x * L->tiles_y);
+  L->cz = choose_cz(L->nzk, L->tiles_x * L->tiles_y, resident);
   L->tiles_z = (L->nzk + L->cz - 1) / L->cz;
   int64_t nt = (int64_t)L->tiles_x * L->tiles_y * L->tiles_z;
-  if (nt > 0x3fffffff) return set_error(PLBM_E_INVALID, "too many tiles");
+  if ((int64_t)L->tiles_x * L->tiles_y * L->nzk > 0x3fffffff) return set_error(PLBM_E_INVALID, "too many tiles");
   L->ntiles = (int)nt;
+  // reduction records are sized for the shortest chunk, so that the byte
+  // count does not depend on the device the lattice is created on
+  const int64_t max_tiles = (int64_t)L->tiles_x * L->tiles_y * L->nzk;
   const uint64_t S = storage_bytes(d->storage);
   // block width of the population layout (Lines<T> in the kernels)
-  const int XB = (int)(128 / S) < 32 ? (int)(128 / S) : 32;
+  const int XB = (int)(128 / S) < PLBM_XB ? (int)(128 / S) : PLBM_XB;
   const uint64_t QB = (uint64_t)XB * S;
   const uint64_t blk = (L->Q * QB + 127) / 128 * 128;  // bytes of one block of XB nodes (Lines<T>::slots)
   L->nxb = (L->nxk + XB - 1) / XB;
@@ -130,7 +151,7 @@ int make_layout(const plbm_lattice_desc* d, Layout* L) {
   L->uprev = off;
   off = align_up(off + (uint64_t)L->D * L->N * 4);
   L->red = off;
-  off = align_up(off + (uint64_t)(L->ntiles + 1) * sizeof(RedRec));
+  off = align_up(off + (uint64_t)(max_tiles + 1) * sizeof(RedRec));
   L->kp = off;
   off = align_up(off + sizeof(KParams));
   L->total = off;
@@ -165,6 +186,28 @@ hipError_t launch_step(const plbm_lattice_desc& d, StepLaunch& a) {
     case PLBM_F16R: return launch_step_f16r(a);
     default: return launch_step_bf16r(a);
   }
+}
+
+// Update workgroups the current device holds at once for this descriptor
+// (CUs x occupancy), or 0 if it cannot be queried.
+int64_t resident_workgroups(const plbm_lattice_desc& d) {
+  const int lat = d.lattice == PLBM_D3Q19 ? 1 : 0;
+  const int last = lat ? 2 : 1;
+  const int walls = d.bc[last] == PLBM_HALFWAY_BB;
+  int blocks = 0, dev = 0, cus = 0;
+  hipError_t e;
+  switch (d.storage) {
+    case PLBM_F64: e = occupancy_step_f64(lat, d.collision, walls, &blocks); break;
+    case PLBM_F32: e = occupancy_step_f32(lat, d.collision, walls, &blocks); break;
+    case PLBM_F16S: e = occupancy_step_f16s(lat, d.collision, walls, &blocks); break;
+    case PLBM_BF16S: e = occupancy_step_bf16s(lat, d.collision, walls, &blocks); break;
+    case PLBM_F16R: e = occupancy_step_f16r(lat, d.collision, walls, &blocks); break;
+    default: e = occupancy_step_bf16r(lat, d.collision, walls, &blocks); break;
+  }
+  if (e != hipSuccess || blocks <= 0) return 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 0;
+  return (int64_t)blocks * cus;
 }
 
 hipError_t launch_aux(const plbm_lattice_desc& d, AuxLaunch& a) {
@@ -325,7 +368,8 @@ int plbm_create(const plbm_lattice_desc* desc, const plbm_lattice_params* params
   if (!out || !params) return set_error(PLBM_E_INVALID, "null argument");
   *out = nullptr;
   Layout lay;
-  int st = make_layout(desc, &lay);
+  if (!desc) return set_error(PLBM_E_INVALID, "null descriptor");
+  int st = make_layout(desc, &lay, resident_workgroups(*desc));
   if (st) return st;
   if (!dev_mem) return set_error(PLBM_E_INVALID, "null device memory");
   if (((uintptr_t)dev_mem) % kAlign) return set_error(PLBM_E_INVALID, "device memory must be 256-byte aligned");

@@ -240,9 +240,12 @@ struct KParams {
 // 16-bit storage, so every block starts on a line and a 32-wide tile row
 // covers whole lines that no other tile touches.  All directions of a node sit
 // at a common offset plus q * QB bytes.
+#ifndef PLBM_XB
+#define PLBM_XB 32
+#endif
 template <class T>
 struct Lines {
-  static constexpr int XB = (128 / (int)sizeof(T)) < 32 ? (128 / (int)sizeof(T)) : 32;
+  static constexpr int XB = (128 / (int)sizeof(T)) < PLBM_XB ? (128 / (int)sizeof(T)) : PLBM_XB;
   static constexpr int QB = XB * (int)sizeof(T);
   template <int Q>
   static constexpr int slots() {

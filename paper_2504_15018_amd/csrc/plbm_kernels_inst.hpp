@@ -31,6 +31,23 @@ hipError_t PLBM_CAT(launch_step_, PLBM_SUFFIX)(const StepLaunch& a) {
   return a.lattice == 1 ? step_for<D3Q19L>(a) : step_for<D2Q9L>(a);
 }
 
+template <class L, int COLL, bool WALLS>
+static hipError_t occ_go(int* blocks) {
+  using TS = TileShape<L>;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      blocks, k_step<L, PLBM_ST, COLL, MODE_STEP, TS::TX, TS::TY, TS::NT, WALLS>, TS::NT, 0);
+}
+
+template <class L>
+static hipError_t occ_for(int coll, int walls, int* blocks) {
+  if (coll == COLL_MRT) return walls ? occ_go<L, COLL_MRT, true>(blocks) : occ_go<L, COLL_MRT, false>(blocks);
+  return walls ? occ_go<L, COLL_BGK, true>(blocks) : occ_go<L, COLL_BGK, false>(blocks);
+}
+
+hipError_t PLBM_CAT(occupancy_step_, PLBM_SUFFIX)(int lattice, int coll, int walls, int* blocks) {
+  return lattice == 1 ? occ_for<D3Q19L>(coll, walls, blocks) : occ_for<D2Q9L>(coll, walls, blocks);
+}
+
 template <class L>
 static hipError_t aux_for(const AuxLaunch& a) {
   dim3 g(a.nblocks), b(256);

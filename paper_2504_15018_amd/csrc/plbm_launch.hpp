@@ -8,6 +8,10 @@
 
 #include "plbm_device.hpp"
 
+#ifndef PLBM_HALO_SPLIT
+#define PLBM_HALO_SPLIT 1
+#endif
+
 namespace plbm {
 
 struct WorkItem;
@@ -20,13 +24,18 @@ struct TileShape;
 #ifndef PLBM_D3_TY
 #define PLBM_D3_TY 8
 #endif
+// With PLBM_HALO_SPLIT the workgroup adds whole waves for the halo ring
+// (D3Q19: (TX+2)(TY+2) - TX TY nodes; D2Q9: the two row ends).
 template <>
 struct TileShape<D3Q19L> {
-  static constexpr int TX = 32, TY = PLBM_D3_TY, NT = 32 * PLBM_D3_TY;
+  static constexpr int TX = 32, TY = PLBM_D3_TY;
+  static constexpr int H = (TX + 2) * (TY + 2) - TX * TY;
+  static constexpr int NT = TX * TY + (PLBM_HALO_SPLIT ? 64 * ((H + 63) / 64) : 0);
 };
 template <>
 struct TileShape<D2Q9L> {
-  static constexpr int TX = 128, TY = 1, NT = 128;
+  static constexpr int TX = 128, TY = 1;
+  static constexpr int NT = TX * TY + (PLBM_HALO_SPLIT ? 64 : 0);
 };
 
 struct StepLaunch {
@@ -72,6 +81,13 @@ hipError_t launch_step_f16r(const StepLaunch&);
 hipError_t launch_step_bf16r(const StepLaunch&);
 hipError_t launch_aux_f16r(const AuxLaunch&);
 hipError_t launch_aux_bf16r(const AuxLaunch&);
+// resident workgroups per CU of the update kernel (hipOccupancy...)
+hipError_t occupancy_step_f64(int lattice, int coll, int walls, int* blocks);
+hipError_t occupancy_step_f32(int lattice, int coll, int walls, int* blocks);
+hipError_t occupancy_step_f16s(int lattice, int coll, int walls, int* blocks);
+hipError_t occupancy_step_bf16s(int lattice, int coll, int walls, int* blocks);
+hipError_t occupancy_step_f16r(int lattice, int coll, int walls, int* blocks);
+hipError_t occupancy_step_bf16r(int lattice, int coll, int walls, int* blocks);
 hipError_t launch_accum(hipStream_t st, int nblocks, int64_t N, int first, const double* in, double* acc);
 hipError_t launch_set_ref(hipStream_t st, int nblocks, const KParams* P, int par, const double* acc);
 hipError_t launch_reduce_final(hipStream_t st, const KParams* P, int ntiles, void* out);

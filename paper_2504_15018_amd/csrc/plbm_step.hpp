@@ -20,6 +20,12 @@
 
 namespace plbm {
 
+#ifndef PLBM_HALO_SPLIT
+#define PLBM_HALO_SPLIT 1  // the halo ring is carried by extra waves of its own
+#endif
+#ifndef PLBM_PREFETCH
+#define PLBM_PREFETCH 2  // plane iterations between issuing a plane's loads and summing it
+#endif
 #ifndef PLBM_MIN_WAVES
 #define PLBM_MIN_WAVES 2  // waves per SIMD the register allocation must allow
 #endif
@@ -245,12 +251,14 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   using T = typename St::T;
   using C = typename St::C;
   constexpr int Q = L::Q, D = L::D, HY = L::HY;
-  static_assert(TX * TY == NT, "one node per thread per plane");
+  constexpr int NI = TX * TY;             // tile nodes: one per interior thread per plane
   constexpr int W2 = TX + 2;
   constexpr int PL = W2 * (TY + 2 * HY);  // LDS plane (tile + halo)
-  constexpr int H = PL - TX * TY;         // halo nodes per plane
+  constexpr int H = PL - NI;              // halo nodes per plane
   constexpr int HW = (H + 63) / 64;       // waves that carry the halo ring
-  static_assert(H <= NT, "halo fits one node per thread");
+  constexpr bool SPLIT = PLBM_HALO_SPLIT != 0;
+  static_assert(NT == (SPLIT ? NI + 64 * HW : NI), "thread count of the tile shape");
+  static_assert(NI % 64 == 0 && H <= NI, "whole interior waves; halo fits");
   constexpr uint32_t TS = sizeof(T);
   constexpr int XB = Lines<T>::XB;
   constexpr int QB = Lines<T>::QB;
@@ -306,6 +314,11 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   // direction q adds q * QB bytes.
   const int t = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(t) >> 6;
+  // with SPLIT, threads t >= NI carry only the halo ring (halo node t - NI);
+  // otherwise the first HW waves carry it besides their tile nodes
+  const bool halo_thread = SPLIT && wave >= NI / 64;
+  const int ti = halo_thread ? 0 : t;
+  const int th = SPLIT ? (halo_thread ? t - NI : H) : t;
   auto node_off = [&](int x, int y) -> uint32_t {
     return (uint32_t)((((y * nxb + x / XB) * QS) * XB + x % XB) * (int)TS);
   };
@@ -314,9 +327,9 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   int ilds, hlds, own, hown;
   bool ivalid;
   {
-    const int lx = t % TX, ly = t / TX;
+    const int lx = ti % TX, ly = ti / TX;
     int gx = x0 + lx, gy = y0 + ly;
-    ivalid = (gx < nx) && (gy < ny);
+    ivalid = (gx < nx) && (gy < ny) && !halo_thread;
     gx = gx < nx ? gx : gx % nx;  // ragged tile: a wrapped duplicate, never stored
     gy = gy < ny ? gy : gy % ny;
     const int xm = gx == 0 ? nx - 1 : gx - 1, xp = gx == nx - 1 ? 0 : gx + 1;
@@ -329,12 +342,12 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
             node_off(cx > 0 ? xm : (cx < 0 ? xp : gx), cy > 0 ? ym : (cy < 0 ? yp : gy));
     ilds = (ly + HY) * W2 + (lx + 1);
     own = gy * nx + gx;
-    soff = ivalid ? ioxy[4] : zdata + (uint32_t)((((t / XB) * QS) * XB + t % XB) * (int)TS);
+    soff = ivalid ? ioxy[4] : zdata + (uint32_t)((((ti / XB) * QS) * XB + ti % XB) * (int)TS);
   }
   {
-    // halo node h = t of the ring around the tile; lanes t >= H of the halo
+    // halo node h of the ring around the tile; lanes h >= H of the halo
     // waves repeat their own node and write psi to a spare LDS slot
-    const int h = t;
+    const int h = th;
     const bool hact = h < H;
     int lx, ly;
     if (HY) {
@@ -569,6 +582,7 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   // population register sets rotate roles (unrolled by three, no copies):
   // plane z is collided while plane z+1 waits with its psi in LDS and the
   // loads of plane z+2 are in flight.
+#if PLBM_PREFETCH == 1
   auto march = [&](auto halo_c) {
     R f0[Q], f1[Q], f2[Q], hb[Q];
     C r0, r1, r2;      // densities
@@ -598,10 +612,108 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     }
     if (z < z1) stepz(z, f1, r1, q1, f0, r0, q0);
   };
-  if (wave < HW)
-    march(BoolC<true>{});
-  else
-    march(BoolC<false>{});
+#else
+  // Loads run a full plane iteration ahead of their use: iteration z issues
+  // plane z+3, collides plane z and sums the density and psi of plane z+2,
+  // whose loads were issued one iteration earlier.  Four population register
+  // sets and two halo sets rotate (unrolled by four, no copies).
+  auto march = [&](auto halo_c) {
+    R fa[Q], fb[Q], fc[Q], fd[Q], ha[Q], hb[Q];
+    C ra, rb, rc, rd;
+    RefT qa = 0, qb = 0, qc = 0, qd = 0, qha = 0, qhb = 0;  // reference densities (LOC)
+    issue(halo_c, z0 - 1, fa, ha, qa, qha);
+    finish(halo_c, z0 - 1, false, fa, ra, qa, ha, qha);
+    issue(halo_c, z0, fa, ha, qa, qha);
+    finish(halo_c, z0, true, fa, ra, qa, ha, qha);
+    issue(halo_c, z0 + 1, fb, ha, qb, qha);
+    finish(halo_c, z0 + 1, true, fb, rb, qb, ha, qha);
+    issue(halo_c, z0 + 2, fc, ha, qc, qha);
+    auto stepz = [&](int z, R* cur, C rcur, RefT qcur, R* f2, C& r2, RefT& q2, R* h2, RefT& qh2, R* pf, RefT& qp,
+                     R* hp, RefT& qhp) {
+      issue(halo_c, z + 3, pf, hp, qp, qhp);
+      __syncthreads();
+      phaseB(z, cur, rcur, qcur);
+      finish(halo_c, z + 2, true, f2, r2, q2, h2, qh2);
+    };
+    int z = z0;
+    for (; z + 3 < z1; z += 4) {
+      stepz(z, fa, ra, qa, fc, rc, qc, ha, qha, fd, qd, hb, qhb);
+      stepz(z + 1, fb, rb, qb, fd, rd, qd, hb, qhb, fa, qa, ha, qha);
+      stepz(z + 2, fc, rc, qc, fa, ra, qa, ha, qha, fb, qb, hb, qhb);
+      stepz(z + 3, fd, rd, qd, fb, rb, qb, hb, qhb, fc, qc, ha, qha);
+    }
+    if (z < z1) {
+      stepz(z, fa, ra, qa, fc, rc, qc, ha, qha, fd, qd, hb, qhb);
+      ++z;
+    }
+    if (z < z1) {
+      stepz(z, fb, rb, qb, fd, rd, qd, hb, qhb, fa, qa, ha, qha);
+      ++z;
+    }
+    if (z < z1) stepz(z, fc, rc, qc, fa, ra, qa, ha, qha, fb, qb, hb, qhb);
+  };
+#endif
+  // Halo waves (SPLIT): pull the ring nodes of a plane, sum their density and
+  // write their psi, with the same barriers as the tile waves and the same
+  // distance between issuing a plane's loads and summing it.
+  auto march_halo = [&]() {
+    R ha[Q], hb[Q];
+    RefT qa = 0, qb = 0;
+    auto hissue = [&](int zl, R* ho, RefT& qh) {
+      const int pz = wrapz(zl);
+      const int zm = pz == 0 ? (WALLS ? 0 : nz - 1) : pz - 1;
+      const int zp = pz == nz - 1 ? (WALLS ? nz - 1 : 0) : pz + 1;
+      pull(hoxy, src + (uint64_t)zm * zblock, src + (uint64_t)pz * zblock, src + (uint64_t)zp * zblock,
+           WALLS && pz == 0, WALLS && pz == nz - 1, ho);
+      if constexpr (LOC) qh = ref_src[(uint32_t)(pz * plane + hown)];
+    };
+    auto hfinish = [&](int zl, const R* ho, RefT qh) {
+      const int slot = ((zl - z0 + 1) & 3) * PL;
+      const C rh = density(ho, as_ref(qh));
+      bool hng;
+      const C ph = psi_eval<C>(eos, (double)rh, &hng);
+      (hlds < 4 * PL ? lds_psi + slot : lds_psi)[hlds] = ph;
+      if constexpr (LOC) (hlds < 4 * PL ? lds_ref + slot : lds_ref)[hlds] = (C)(RefT)rh;
+    };
+    for (int zl = z0 - 1; zl <= z0 + 1; ++zl) {
+      hissue(zl, ha, qa);
+      hfinish(zl, ha, qa);
+    }
+    int z = z0;
+#if PLBM_PREFETCH == 1
+    for (; z < z1; ++z) {
+      hissue(z + 2, ha, qa);
+      __syncthreads();
+      hfinish(z + 2, ha, qa);
+    }
+#else
+    hissue(z0 + 2, ha, qa);
+    for (; z + 1 < z1; z += 2) {
+      hissue(z + 3, hb, qb);
+      __syncthreads();
+      hfinish(z + 2, ha, qa);
+      hissue(z + 4, ha, qa);
+      __syncthreads();
+      hfinish(z + 3, hb, qb);
+    }
+    if (z < z1) {
+      hissue(z + 3, hb, qb);
+      __syncthreads();
+      hfinish(z + 2, ha, qa);
+    }
+#endif
+  };
+  if constexpr (SPLIT) {
+    if (halo_thread)
+      march_halo();
+    else
+      march(BoolC<false>{});
+  } else {
+    if (wave < HW)
+      march(BoolC<true>{});
+    else
+      march(BoolC<false>{});
+  }
 
   if (MODE == MODE_REDUCE) {
     if (psi_neg) acc_flags |= 4;
