@@ -35,12 +35,15 @@ KERNEL_SOURCES = ["plbm_device.hpp", "plbm_step.hpp", "plbm_launch.hpp", "plbm_k
 
 
 def kernel_source_hash():
-    """sha256 over the sources of the float32 step kernel (identifies the kernel a profile was taken of)."""
+    """sha256 over the sources and compile flags of the float32 step kernel (identifies the kernel a profile
+    was taken of)."""
     import hashlib
+    from paper_2504_15018_amd import build
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2504_15018_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(build.COMMON[1:] + build.SOURCES["plbm_k_f32.hip"]).encode())
     return h.hexdigest()[:16]
 
 

@@ -27,12 +27,13 @@ COMMON = [
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 SOURCES = {
-    # Per storage, the kernel shape measured fastest on MI355X (256^3 D3Q19 MRT):
-    # float32 and float64 carry the halo ring on waves of their own (float64
-    # with loads one plane ahead to stay within 256 registers); the 16-bit
-    # formats keep the halo on two of the tile waves.
+    # Per storage, the kernel shape measured fastest on MI355X (256^3 D3Q19
+    # BGK/MRT, 384x384x128 channel): float32 and float64 carry the halo ring on
+    # waves of their own (float32 with 32 x 16 tiles, ten waves per workgroup;
+    # float64 with loads one plane ahead to stay within 256 registers); the
+    # 16-bit formats keep 32 x 8 tiles and the halo on two of the tile waves.
     "plbm_k_f64.hip": ["-ffp-contract=off", "-DPLBM_PREFETCH=1"],
-    "plbm_k_f32.hip": [],
+    "plbm_k_f32.hip": ["-DPLBM_D3_TY=16", "-DPLBM_MIN_WAVES=3"],
     "plbm_k_f16s.hip": ["-DPLBM_HALO_SPLIT=0", "-DPLBM_PREFETCH=1"],
     "plbm_k_bf16s.hip": ["-DPLBM_HALO_SPLIT=0", "-DPLBM_PREFETCH=1"],
     "plbm_k_f16r.hip": ["-DPLBM_HALO_SPLIT=0", "-DPLBM_PREFETCH=1"],

@@ -8,15 +8,19 @@
 
 namespace plbm {
 
+#ifndef PLBM_LDS_PAD
+#define PLBM_LDS_PAD 0  // extra LDS bytes per workgroup (limits workgroups per CU)
+#endif
+
 template <class L, int COLL, int MODE>
 static hipError_t go_step(const StepLaunch& a) {
   using TS = TileShape<L>;
   if (a.walls)
     hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, TS::NT, true>), dim3(a.nblocks), dim3(TS::NT),
-                       0, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
+                       PLBM_LDS_PAD, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
   else
     hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, TS::NT, false>), dim3(a.nblocks),
-                       dim3(TS::NT), 0, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
+                       dim3(TS::NT), PLBM_LDS_PAD, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
   return hipGetLastError();
 }
 
@@ -35,7 +39,7 @@ template <class L, int COLL, bool WALLS>
 static hipError_t occ_go(int* blocks) {
   using TS = TileShape<L>;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks, k_step<L, PLBM_ST, COLL, MODE_STEP, TS::TX, TS::TY, TS::NT, WALLS>, TS::NT, 0);
+      blocks, k_step<L, PLBM_ST, COLL, MODE_STEP, TS::TX, TS::TY, TS::NT, WALLS>, TS::NT, PLBM_LDS_PAD);
 }
 
 template <class L>
@@ -43,6 +47,8 @@ static hipError_t occ_for(int coll, int walls, int* blocks) {
   if (coll == COLL_MRT) return walls ? occ_go<L, COLL_MRT, true>(blocks) : occ_go<L, COLL_MRT, false>(blocks);
   return walls ? occ_go<L, COLL_BGK, true>(blocks) : occ_go<L, COLL_BGK, false>(blocks);
 }
+
+int PLBM_CAT(tile_ty_, PLBM_SUFFIX)() { return TileShape<D3Q19L>::TY; }
 
 hipError_t PLBM_CAT(occupancy_step_, PLBM_SUFFIX)(int lattice, int coll, int walls, int* blocks) {
   return lattice == 1 ? occ_for<D3Q19L>(coll, walls, blocks) : occ_for<D2Q9L>(coll, walls, blocks);

@@ -81,6 +81,14 @@ hipError_t launch_step_f16r(const StepLaunch&);
 hipError_t launch_step_bf16r(const StepLaunch&);
 hipError_t launch_aux_f16r(const AuxLaunch&);
 hipError_t launch_aux_bf16r(const AuxLaunch&);
+// D3Q19 tile rows of each storage's kernels (the tile shape is compiled per
+// storage translation unit)
+int tile_ty_f64();
+int tile_ty_f32();
+int tile_ty_f16s();
+int tile_ty_bf16s();
+int tile_ty_f16r();
+int tile_ty_bf16r();
 // resident workgroups per CU of the update kernel (hipOccupancy...)
 hipError_t occupancy_step_f64(int lattice, int coll, int walls, int* blocks);
 hipError_t occupancy_step_f32(int lattice, int coll, int walls, int* blocks);
