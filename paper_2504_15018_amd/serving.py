@@ -44,6 +44,7 @@ class Request:
         self.lat = None
         self.slot = None
         self.params = None
+        self.error = None
 
     @property
     def nodes(self):
@@ -53,7 +54,7 @@ class Request:
         return {"id": self.id, "arrival": self.arrival, "admit": self.admit, "done": self.done,
                 "latency": None if self.done is None else self.done - self.arrival, "steps": self.steps,
                 "status": self.status, "bytes": self.bytes, "nodes": self.nodes, "lattice": self.lattice,
-                "dims": self.dims, "T_over_Tc": self.T_over_Tc, "residual": self.residual}
+                "dims": self.dims, "T_over_Tc": self.T_over_Tc, "residual": self.residual, "error": self.error}
 
 
 def admissible(queue, n_resident, used, budget, max_slots):
@@ -101,9 +102,10 @@ class Server:
         self.peak_resident = 0
 
     def close(self):
+        """Cancel what is still resident (its `done` stays None) and release the batch."""
         self.stream.synchronize()
         for r in list(self.resident.values()):
-            self._retire(r, "cancelled", time.perf_counter())
+            self._retire(r, "cancelled", None)
         N.plbm_batch_destroy(self.batch)
         self.batch = None
 
@@ -116,11 +118,11 @@ class Server:
         req.params = N.plbm_params_pr_lattice(req.T_over_Tc, 0.326, 2.0, 1.0, 1.0, 1.0)
         lat = Lattice(req.lattice, req.dims, req.params, collision=self.collision, storage=self.storage,
                       stream=self.stream)
+        req.lat = lat
         centre = [n / 2.0 for n in req.dims]
         lat.init_shape(N.PLBM_SHAPE_DROPLET, req.params.rho_l, req.params.rho_v, W=self.width, R=req.radius,
                        centre=centre)
         lat.reduce()  # stores u(0) for the first residual
-        req.lat = lat
         req.slot = N.plbm_batch_attach(self.batch, lat.h)
         req.admit = now
         req.status = "running"
@@ -159,7 +161,15 @@ class Server:
                 queue.append(pending[i])
                 i += 1
             for _ in range(admissible(queue, len(self.resident), self.used, self.budget, self.max_slots)):
-                self._admit(queue.pop(0), time.perf_counter() - t0)
+                req = queue.pop(0)
+                try:
+                    self._admit(req, time.perf_counter() - t0)
+                except N.PlbmError as e:  # e.g. no coexistence at this T/Tc: refuse the request, keep serving
+                    if req.lat is not None:
+                        req.lat.close()
+                        req.lat = None
+                    req.status = "rejected"
+                    req.error = str(e)
             if not self.resident:
                 if i < len(pending):
                     time.sleep(max(0.0, min(pending[i].arrival - now, 0.01)))

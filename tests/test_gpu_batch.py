@@ -20,6 +20,8 @@ SPECS = [
     ("D2Q9", (150, 40), "bgk", "f32", False, 3),
     ("D2Q9", (64, 64), "mrt", "f64", False, 4),
     ("D3Q19", (36, 20, 10), "mrt", "f32", False, 5),
+    ("D3Q19", (36, 18, 12), "mrt", "f16r", True, 6),
+    ("D2Q9", (96, 40), "bgk", "bf16s", False, 7),
 ]
 
 
@@ -70,8 +72,8 @@ def test_batch_matches_solo_bitwise_with_joins_and_leaves():
     mixed = [_make(s, stream=stream) for s in SPECS]
     b = Batch(8, 4096, stream)
     slots = {}
-    # lattices 0..2 start together; 3 joins after 7 steps; 1 leaves after 12; 4 joins at 12
-    for k in (0, 1, 2):
+    # lattices 0..2, 5, 6 start together; 3 joins after 7 steps; 1 leaves after 12; 4 joins at 12
+    for k in (0, 1, 2, 5, 6):
         slots[k] = b.attach(mixed[k])
     b.step(7)
     slots[3] = b.attach(mixed[3])
@@ -81,7 +83,7 @@ def test_batch_matches_solo_bitwise_with_joins_and_leaves():
     b.step(9)  # odd count: graph pairs plus a single launch
     b.step(1)
     stream.synchronize()
-    steps = {0: 22, 1: 12, 2: 22, 3: 15, 4: 10}
+    steps = {0: 22, 1: 12, 2: 22, 3: 15, 4: 10, 5: 22, 6: 22}
     for k, lat in enumerate(solo):
         lat.step(steps[k])
     for k in range(len(SPECS)):

@@ -44,3 +44,20 @@ def test_serving_small_stream_matches_solo_runs():
         r.lat.close()
     assert big.status in ("converged", "capped")
     srv.close()
+
+
+def test_serving_refuses_a_request_without_coexistence_and_serves_the_rest():
+    """T/Tc >= 1 has no liquid-vapour coexistence: the parameter solve fails, the request is refused, the
+    loop keeps serving the others."""
+    require_gpu()
+    from paper_2504_15018_amd.serving import Request, Server
+
+    fmt("serving_reject")
+    reqs = [Request(0, 0.0, "D2Q9", (48, 48), 0.85, 10.0), Request(1, 0.0, "D2Q9", (40, 40), 1.1, 8.0),
+            Request(2, 0.0, "D3Q19", (16, 16, 16), 0.85, 4.0)]
+    srv = Server(budget_bytes=1 << 34, max_slots=4, max_tiles=4096, check_every=50, tol=1e-6, max_steps=4000)
+    out = srv.run(reqs, time_limit=60)
+    srv.close()
+    assert reqs[1].status == "rejected" and reqs[1].error
+    assert reqs[0].status in ("converged", "capped") and reqs[2].status in ("converged", "capped")
+    assert out["rejected"] == 1 and out["unfinished"] == 0
