@@ -32,12 +32,14 @@ SOURCES = {
     # waves of their own (float32 with 32 x 16 tiles, ten waves per workgroup;
     # float64 with loads one plane ahead to stay within 256 registers); the
     # 16-bit formats keep 32 x 8 tiles and the halo on two of the tile waves.
+    # Populations are stored with the non-temporal hint except by bfloat16 and
+    # the locally shifted formats (slower with it).
     "plbm_k_f64.hip": ["-ffp-contract=off", "-DPLBM_PREFETCH=1"],
     "plbm_k_f32.hip": ["-DPLBM_D3_TY=16", "-DPLBM_MIN_WAVES=3"],
     "plbm_k_f16s.hip": ["-DPLBM_HALO_SPLIT=0", "-DPLBM_PREFETCH=1"],
-    "plbm_k_bf16s.hip": ["-DPLBM_HALO_SPLIT=0", "-DPLBM_PREFETCH=1"],
-    "plbm_k_f16r.hip": ["-DPLBM_HALO_SPLIT=0", "-DPLBM_PREFETCH=1"],
-    "plbm_k_bf16r.hip": ["-DPLBM_HALO_SPLIT=0", "-DPLBM_PREFETCH=1"],
+    "plbm_k_bf16s.hip": ["-DPLBM_HALO_SPLIT=0", "-DPLBM_PREFETCH=1", "-DPLBM_NT_STORE=0"],
+    "plbm_k_f16r.hip": ["-DPLBM_HALO_SPLIT=0", "-DPLBM_PREFETCH=1", "-DPLBM_NT_STORE=0"],
+    "plbm_k_bf16r.hip": ["-DPLBM_HALO_SPLIT=0", "-DPLBM_PREFETCH=1", "-DPLBM_NT_STORE=0"],
     "plbm_api.hip": [],
     "plbm_params.cpp": ["-x", "hip", "-ffp-contract=off"],
 }

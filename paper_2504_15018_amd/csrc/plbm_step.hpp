@@ -73,11 +73,19 @@ __device__ __forceinline__ T gld(const void* base, uint32_t byte_off) {
   typedef const __attribute__((address_space(1))) T gT;
   return *(gT*)((gchar*)base + byte_off);
 }
+
+#ifndef PLBM_NT_STORE
+#define PLBM_NT_STORE 1  // populations stored with the non-temporal hint (read again only next step)
+#endif
 template <class T>
 __device__ __forceinline__ void gst(void* base, uint32_t byte_off, T v) {
   typedef __attribute__((address_space(1))) char gchar;
   typedef __attribute__((address_space(1))) T gT;
+#if PLBM_NT_STORE
+  __builtin_nontemporal_store(v, (gT*)((gchar*)base + byte_off));
+#else
   *(gT*)((gchar*)base + byte_off) = v;
+#endif
 }
 
 // psi stencil and interaction force at one node (Sec. II):
