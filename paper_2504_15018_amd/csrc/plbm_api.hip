@@ -45,14 +45,14 @@ uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 int storage_bytes(int storage) { return storage == PLBM_F64 ? 8 : storage == PLBM_F32 ? 4 : 2; }
 
-int d3_tile_ty(int storage) {
+void d3_tile_shape(int storage, int* tx, int* ty) {
   switch (storage) {
-    case PLBM_F64: return tile_ty_f64();
-    case PLBM_F32: return tile_ty_f32();
-    case PLBM_F16S: return tile_ty_f16s();
-    case PLBM_BF16S: return tile_ty_bf16s();
-    case PLBM_F16R: return tile_ty_f16r();
-    default: return tile_ty_bf16r();
+    case PLBM_F64: return tile_shape_f64(tx, ty);
+    case PLBM_F32: return tile_shape_f32(tx, ty);
+    case PLBM_F16S: return tile_shape_f16s(tx, ty);
+    case PLBM_BF16S: return tile_shape_bf16s(tx, ty);
+    case PLBM_F16R: return tile_shape_f16r(tx, ty);
+    default: return tile_shape_bf16r(tx, ty);
   }
 }
 
@@ -123,8 +123,12 @@ int make_layout(const plbm_lattice_desc* d, Layout* L, int64_t resident = 0) {
   L->nzk = is2d ? d->ny : d->nz;
   L->N = (int64_t)d->nx * d->ny * d->nz;
   if (L->N > 0x7fffffffLL) return set_error(PLBM_E_INVALID, "lattice larger than 2^31 - 1 nodes");
-  L->tx = is2d ? TileShape<D2Q9L>::TX : TileShape<D3Q19L>::TX;
-  L->ty = is2d ? TileShape<D2Q9L>::TY : d3_tile_ty(d->storage);
+  if (is2d) {
+    L->tx = TileShape<D2Q9L>::TX;
+    L->ty = TileShape<D2Q9L>::TY;
+  } else {
+    d3_tile_shape(d->storage, &L->tx, &L->ty);
+  }
   L->tiles_x = (L->nxk + L->tx - 1) / L->tx;
   L->tiles_y = (L->nyk + L->ty - 1) / L->ty;
   L->cz = choose_cz(L->nzk, L->tiles_x * L->tiles_y, resident);

@@ -48,7 +48,10 @@ static hipError_t occ_for(int coll, int walls, int* blocks) {
   return walls ? occ_go<L, COLL_BGK, true>(blocks) : occ_go<L, COLL_BGK, false>(blocks);
 }
 
-int PLBM_CAT(tile_ty_, PLBM_SUFFIX)() { return TileShape<D3Q19L>::TY; }
+void PLBM_CAT(tile_shape_, PLBM_SUFFIX)(int* tx, int* ty) {
+  *tx = TileShape<D3Q19L>::TX;
+  *ty = TileShape<D3Q19L>::TY;
+}
 
 hipError_t PLBM_CAT(occupancy_step_, PLBM_SUFFIX)(int lattice, int coll, int walls, int* blocks) {
   return lattice == 1 ? occ_for<D3Q19L>(coll, walls, blocks) : occ_for<D2Q9L>(coll, walls, blocks);

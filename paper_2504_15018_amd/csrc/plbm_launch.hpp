@@ -21,6 +21,9 @@ struct ShapeK;
 // (one node per thread per plane); D2Q9 rows of 128 nodes per 128 threads.
 template <class L>
 struct TileShape;
+#ifndef PLBM_D3_TX
+#define PLBM_D3_TX 32
+#endif
 #ifndef PLBM_D3_TY
 #define PLBM_D3_TY 8
 #endif
@@ -28,7 +31,7 @@ struct TileShape;
 // (D3Q19: (TX+2)(TY+2) - TX TY nodes; D2Q9: the two row ends).
 template <>
 struct TileShape<D3Q19L> {
-  static constexpr int TX = 32, TY = PLBM_D3_TY;
+  static constexpr int TX = PLBM_D3_TX, TY = PLBM_D3_TY;
   static constexpr int H = (TX + 2) * (TY + 2) - TX * TY;
   static constexpr int NT = TX * TY + (PLBM_HALO_SPLIT ? 64 * ((H + 63) / 64) : 0);
 };
@@ -81,14 +84,14 @@ hipError_t launch_step_f16r(const StepLaunch&);
 hipError_t launch_step_bf16r(const StepLaunch&);
 hipError_t launch_aux_f16r(const AuxLaunch&);
 hipError_t launch_aux_bf16r(const AuxLaunch&);
-// D3Q19 tile rows of each storage's kernels (the tile shape is compiled per
+// D3Q19 tile shape (x nodes, y rows) of each storage's kernels (compiled per
 // storage translation unit)
-int tile_ty_f64();
-int tile_ty_f32();
-int tile_ty_f16s();
-int tile_ty_bf16s();
-int tile_ty_f16r();
-int tile_ty_bf16r();
+void tile_shape_f64(int* tx, int* ty);
+void tile_shape_f32(int* tx, int* ty);
+void tile_shape_f16s(int* tx, int* ty);
+void tile_shape_bf16s(int* tx, int* ty);
+void tile_shape_f16r(int* tx, int* ty);
+void tile_shape_bf16r(int* tx, int* ty);
 // resident workgroups per CU of the update kernel (hipOccupancy...)
 hipError_t occupancy_step_f64(int lattice, int coll, int walls, int* blocks);
 hipError_t occupancy_step_f32(int lattice, int coll, int walls, int* blocks);
