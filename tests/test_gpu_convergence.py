@@ -219,3 +219,59 @@ def test_galilean_planar_interface_converges_on_the_paper_grids():
     fmt("galilean_orders", **{k: f"{v:.2f}" for k, v in orders.items()})
     for k, v in orders.items():
         assert v >= 1.7, (k, v)
+
+
+def test_two_phase_channel_converges_on_the_paper_grids():
+    """Sec. VI.D, Table IV: liquid below, vapour above, half-way bounce-back plates at y = -1/2 and
+    N_y - 1/2, F_x = 1e6 N/m^3, grids N_x x N_y = 5 x 100 ... 25 x 500 with xi = 1.5 ... 7.5.  The steady
+    u_x(y) is compared (eq. relative_norms, every node) with the solution of d/dy(mu du/dy) = -F_x, no slip at
+    the plates, mu = rho nu(rho) evaluated on the simulated density profile (the paper prints no formula; this
+    is the semi-analytic reference); the norms converge at second order.  Reading: tau_l = 1 instead of 0.56
+    (the steady profile in lattice units is compared with the reference for the same viscosities, and the
+    viscous time H^2 / nu that sets the run length is 8 times shorter)."""
+    require_gpu()
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+    grids = [(5, 100, 1.5), (10, 200, 3.0), (15, 300, 4.5), (20, 400, 6.0), (25, 500, 7.5)]
+    L1, L2, Li = [], [], []
+    for nx, ny, xi in grids:
+        prm = _si_params(ny, xi, 1.0, 10e-6, bf=(1e6, 0.0, 0.0))
+        F = prm.body_force[0]
+        lat = Lattice("D2Q9", (nx, ny), prm, collision="bgk", storage="f64", walls=True)
+        lat.init_shape(N.PLBM_SHAPE_LAYERS, prm.rho_l, prm.rho_v, W=2.0 * xi, level=ny / 2.0, axis=1)
+        lat.reduce()
+        nu_l = (prm.tau_l - 0.5) / 3.0
+        t_slow = ny * ny / (np.pi ** 2 * nu_l)
+        steps = 0
+        while steps < 20_000_000:
+            lat.step(20000)
+            steps += 20000
+            d = lat.reduce()
+            if d.max_du_per_step * t_slow < 1e-6 * d.max_u:
+                break
+        rho, u = lat.moments()
+        lat.close()
+        assert d.flags == 0
+        assert np.all(rho == rho[:, :1]) and np.all(u == u[:, :, :1])  # laterally uniform
+        col = rho[:, 0]
+        s_nodes = np.arange(ny) + 0.5  # distance of node j from the lower wall
+        tau_slope = (prm.tau_l - prm.tau_v) / (prm.rho_l - prm.rho_v)
+
+        def rho_of_y(s):
+            return np.interp(s, s_nodes, col)
+
+        def nu_of_rho(r):
+            return (prm.tau_v + (r - prm.rho_v) * tau_slope - 0.5) / 3.0
+
+        ref = A.channel_velocity(s_nodes, rho_of_y, nu_of_rho, F, float(ny), n_quad=200001)
+        n1_, n2_, ni_ = NO.relative_norms(u[0], np.broadcast_to(ref[:, None], u[0].shape))
+        L1.append(n1_)
+        L2.append(n2_)
+        Li.append(ni_)
+        fmt("channel_grid", ny=ny, steps=steps, u_max=f"{float(u[0].max()):.4e}", L1=f"{n1_:.3e}", L2=f"{n2_:.3e}",
+            Linf=f"{ni_:.3e}")
+    lx = np.log([g[1] for g in grids])
+    orders = {k: -np.polyfit(lx, np.log(v), 1)[0] for k, v in (("L1", L1), ("L2", L2), ("Linf", Li))}
+    fmt("channel_orders", **{k: f"{v:.2f}" for k, v in orders.items()})
+    for k, v in orders.items():
+        assert v >= 1.7, (k, v)
