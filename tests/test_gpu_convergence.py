@@ -136,7 +136,7 @@ def test_droplet_spurious_currents_converge_on_the_paper_grids():
         assert abs(got / paper - 1.0) <= 0.10, (got, paper)
 
 
-def _si_params(n_lat, xi_lat, tau_l, L, bf=(0.0, 0.0, 0.0)):
+def _si_params(n_lat, xi_lat, tau_l, L, bf=(0.0, 0.0, 0.0), gamma=7.58e-3):
     """R134a at 30 C (Table I) through the SI front end: L_phs = L, L_lat = n_lat, rho_l,lat = 1.187,
     interface width xi_lat lattice spacings."""
     import json
@@ -148,7 +148,7 @@ def _si_params(n_lat, xi_lat, tau_l, L, bf=(0.0, 0.0, 0.0)):
     ph.eos = N.PLBM_EOS_PAPER
     ph.rho_v, ph.rho_l = t["rho_v_kg_m3"], t["rho_l_kg_m3"]
     ph.nu_v, ph.nu_l = t["nu_v_mm2_s"] * 1e-6, t["nu_l_mm2_s"] * 1e-6
-    ph.gamma, ph.xi, ph.L = 7.58e-3, xi_lat * L / n_lat, L
+    ph.gamma, ph.xi, ph.L = gamma, xi_lat * L / n_lat, L
     for a in range(3):
         ph.body_force[a] = bf[a]
     m = N.plbm_lattice_map()
@@ -275,3 +275,78 @@ def test_two_phase_channel_converges_on_the_paper_grids():
     fmt("channel_orders", **{k: f"{v:.2f}" for k, v in orders.items()})
     for k, v in orders.items():
         assert v >= 1.7, (k, v)
+
+
+# Sec. VI.B, Fig. (SurfaceTension): surface tension gamma, liquid relaxation time, grid (N, xi in spacings),
+# and the relative tolerance on the recovered gamma.  kappa follows from eq. (surface_tension); the paper
+# reaches gamma_2 and gamma_4 through tau_l with kappa near one, and gamma_1, gamma_5 through kappa itself
+# (0.0923 and 5.698), which it finds less accurate on the coarse grid and better on a finer one (measured
+# here: gamma_3 -1.9 %, gamma_2 -1.2 %, gamma_4 -4.0 %, gamma_1 +37 % on N = 100 and +2.6 % on N = 200,
+# gamma_5 +9.7 %).
+LAPLACE_CASES = [
+    (7.58e-3, 0.56, 100, 1.5, 0.05),
+    (0.758e-3, 0.68, 100, 1.5, 0.05),
+    (75.8e-3, 0.52, 100, 1.5, 0.05),
+    (0.0758e-3, 0.68, 100, 1.5, 0.50),
+    (0.0758e-3, 0.68, 200, 3.0, 0.15),
+    (379e-3, 0.52, 100, 1.5, 0.30),
+]
+
+
+@pytest.mark.parametrize("gamma,tau_l,n,xi,tol", LAPLACE_CASES, ids=lambda v: f"{v}")
+def test_young_laplace_recovers_the_imposed_surface_tension(gamma, tau_l, n, xi, tol):
+    """Droplets of diameter 3, 4, 5 and 6 um in a 10 um periodic box: Delta p (p_EOS at the centre minus the
+    far field) against 1/R_eq (R_eq from the equivalent area) is a line through the origin whose slope is the
+    surface tension; it must match the imposed gamma (in lattice units) within `tol`."""
+    require_gpu()
+    from oracle import eos as E
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+    prm = _si_params(n, xi, tau_l, 10e-6, gamma=gamma)
+    eos = E.PaperEOS(prm.K, prm.eos_rho_v, prm.eos_rho_l)
+    inv_r, dps = [], []
+    for D in (3e-6, 4e-6, 5e-6, 6e-6):
+        R0 = D / 2 / (10e-6 / n)
+        lat = Lattice("D2Q9", (n, n), prm, collision="bgk", storage="f64")
+        lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=2.0 * xi, R=R0, centre=[n / 2.0, n / 2.0])
+        lat.reduce()
+        steps = 0
+        while steps < 2_000_000:
+            lat.step(5000)
+            steps += 5000
+            d = lat.reduce()
+            if d.max_du_per_step * 1e5 < 1e-4 * d.max_u:
+                break
+        rho, _ = lat.moments()
+        lat.close()
+        assert d.flags == 0
+        r_in, r_out = rho[n // 2, n // 2], rho[0, 0]
+        area = float(np.sum((rho - r_out) / (r_in - r_out)))
+        inv_r.append(1.0 / np.sqrt(area / np.pi))
+        dps.append(eos.p(r_in) - eos.p(r_out))
+    inv_r, dps = np.array(inv_r), np.array(dps)
+    slope = float(np.sum(inv_r * dps) / np.sum(inv_r * inv_r))  # least squares through the origin
+    fmt("laplace", gamma=gamma, kappa=f"{prm.kappa:.4f}", n=n, gamma_lat=f"{prm.gamma_lat:.4e}",
+        fitted=f"{slope:.4e}", rel=f"{slope / prm.gamma_lat - 1:.3e}")
+    assert abs(slope / prm.gamma_lat - 1.0) <= tol
+
+
+def test_surface_tension_beyond_the_stable_range_is_flagged():
+    """Sec. VI.B: 758 mN/m (kappa ~ 11 at tau_l = 0.52) made the paper's run unstable.  Here too the droplet
+    blows up, and the reduction's health flags report it instead of the run silently producing NaN."""
+    require_gpu()
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+    prm = _si_params(100, 1.5, 0.52, 10e-6, gamma=758e-3)
+    lat = Lattice("D2Q9", (100, 100), prm, collision="bgk", storage="f64")
+    lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=3.0, R=25.0, centre=[50.0, 50.0])
+    flags, steps = 0, 0
+    while steps < 400_000 and not flags & (N.PLBM_FLAG_NAN | N.PLBM_FLAG_RHO_NONPOS):
+        lat.step(2000)
+        steps += 2000
+        flags = lat.reduce(allow_unstable=True).flags
+    fmt("unstable_kappa", kappa=f"{prm.kappa:.3f}", steps=steps, flags=flags)
+    assert flags & (N.PLBM_FLAG_NAN | N.PLBM_FLAG_RHO_NONPOS)
+    with pytest.raises(N.PlbmError):
+        lat.reduce()
+    lat.close()
