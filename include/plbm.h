@@ -272,10 +272,13 @@ void plbm_destroy(plbm_lattice* lat);
  * device buffer of plbm_batch_bytes(max_slots, max_tiles) bytes and is
  * rewritten on the first step after an attach or detach.  plbm_batch_step(n)
  * enqueues n steps of every attached lattice on the batch's stream (pairs of
- * steps replayed from a captured HIP graph).  Attached lattices must not be
- * stepped through their own handles meanwhile.  Results are bitwise identical
- * to stepping each lattice alone.
- * Errors: PLBM_E_INVALID (bad slot, lattice already attached),
+ * steps replayed from a captured HIP graph).  Results are bitwise identical
+ * to stepping each lattice alone.  A lattice belongs to at most one batch at a
+ * time: while attached, plbm_step, plbm_init_* and plbm_write_populations on
+ * its own handle return PLBM_E_INVALID (reads stay allowed).  plbm_destroy of
+ * an attached lattice detaches it first; plbm_batch_destroy releases every
+ * lattice still attached.
+ * Errors: PLBM_E_INVALID (bad slot, lattice attached to a batch already),
  * PLBM_E_NOMEM (dev_bytes too small, no free slot, more than max_tiles tiles). */
 int plbm_batch_bytes(int32_t max_slots, int64_t max_tiles, uint64_t* bytes);
 int plbm_batch_create(int32_t max_slots, int64_t max_tiles, void* dev_mem, uint64_t dev_bytes, void* hip_stream,

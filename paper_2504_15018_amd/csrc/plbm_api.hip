@@ -188,9 +188,20 @@ struct plbm_lattice {
   bool has_red;
   hipGraphExec_t graph2;  // two steps (phase 0, phase 1)
   bool has_graph;
+  plbm_batch* batch;  // the batch the lattice is attached to, or null
+  int32_t slot;
 };
 
+static void batch_forget(plbm_batch* b, int32_t slot);
+
 namespace {
+
+// Calls that change a lattice's state are refused while a batch owns it.
+int check_free(plbm_lattice* L) {
+  if (!L) return set_error(PLBM_E_INVALID, "null lattice");
+  if (L->batch) return set_error(PLBM_E_INVALID, "lattice is attached to a batch (slot %d); detach it first", L->slot);
+  return PLBM_OK;
+}
 
 hipError_t launch_step(const plbm_lattice_desc& d, StepLaunch& a) {
   switch (d.storage) {
@@ -405,6 +416,8 @@ int plbm_create(const plbm_lattice_desc* desc, const plbm_lattice_params* params
   L->t_red = 0;
   L->has_red = false;
   L->has_graph = false;
+  L->batch = nullptr;
+  L->slot = -1;
   L->kp_dev = reinterpret_cast<KParams*>(L->mem + lay.kp);
   fill_kparams(L);
   hipError_t e = hipMemcpyAsync(L->kp_dev, &L->kp, sizeof(KParams), hipMemcpyHostToDevice, L->stream);
@@ -419,7 +432,7 @@ int plbm_create(const plbm_lattice_desc* desc, const plbm_lattice_params* params
 }
 
 int plbm_init_fields(plbm_lattice* L, const double* rho, const double* u) {
-  if (check_lat(L)) return PLBM_E_INVALID;
+  if (check_free(L)) return PLBM_E_INVALID;
   if (!rho) return set_error(PLBM_E_INVALID, "null rho");
   const int64_t N = L->lay.N;
   double* aux = aux_ptr(L);
@@ -434,7 +447,7 @@ int plbm_init_fields(plbm_lattice* L, const double* rho, const double* u) {
 }
 
 int plbm_init_shape(plbm_lattice* L, const plbm_shape* s) {
-  if (check_lat(L)) return PLBM_E_INVALID;
+  if (check_free(L)) return PLBM_E_INVALID;
   if (!s || s->kind < 0 || s->kind > 2 || !(s->W > 0)) return set_error(PLBM_E_INVALID, "bad shape");
   if (s->axis < 0 || s->axis >= L->lay.D) return set_error(PLBM_E_INVALID, "shape axis out of range");
   ShapeK k;
@@ -458,7 +471,7 @@ int plbm_init_shape(plbm_lattice* L, const plbm_shape* s) {
 }
 
 int plbm_step(plbm_lattice* L, int64_t n) {
-  if (check_lat(L)) return PLBM_E_INVALID;
+  if (check_free(L)) return PLBM_E_INVALID;
   if (n < 0) return set_error(PLBM_E_INVALID, "negative step count");
   // long runs replay a captured two-step graph; short ones launch directly
   // (the legacy null stream cannot be captured)
@@ -518,7 +531,7 @@ int plbm_read_populations(plbm_lattice* L, double* f) {
 }
 
 int plbm_write_populations(plbm_lattice* L, const double* f) {
-  if (check_lat(L)) return PLBM_E_INVALID;
+  if (check_free(L)) return PLBM_E_INVALID;
   if (!f) return set_error(PLBM_E_INVALID, "null input");
   const int64_t N = L->lay.N;
   double* aux = aux_ptr(L);
@@ -586,6 +599,7 @@ int plbm_reduce(plbm_lattice* L, plbm_diag* out) {
 
 void plbm_destroy(plbm_lattice* L) {
   if (!L) return;
+  if (L->batch) batch_forget(L->batch, L->slot);  // leaves the batch it was attached to
   if (L->has_graph) (void)hipGraphExecDestroy(L->graph2);
   delete L;
 }
@@ -624,6 +638,15 @@ uint64_t batch_layout(int max_slots, int64_t max_tiles, uint64_t* off_work) {
   off = align_up(off + (uint64_t)max_tiles * sizeof(WorkItem));
   return off;
 }
+
+}  // namespace
+
+static void batch_forget(plbm_batch* b, int32_t slot) {
+  b->lat[slot] = nullptr;
+  b->dirty = true;
+}
+
+namespace {
 
 int batch_rebuild(plbm_batch* b) {
   if (!b->dirty) return PLBM_OK;
@@ -724,12 +747,13 @@ int plbm_batch_create(int32_t max_slots, int64_t max_tiles, void* dev_mem, uint6
 
 int plbm_batch_attach(plbm_batch* b, plbm_lattice* L, int32_t* slot) {
   if (!b || !L || !slot) return set_error(PLBM_E_INVALID, "null argument");
-  for (int s = 0; s < b->max_slots; ++s)
-    if (b->lat[s] == L) return set_error(PLBM_E_INVALID, "lattice already attached");
+  if (L->batch) return set_error(PLBM_E_INVALID, "lattice already attached to a batch");
   for (int s = 0; s < b->max_slots; ++s) {
     if (!b->lat[s]) {
       b->lat[s] = L;
       b->dirty = true;
+      L->batch = b;
+      L->slot = s;
       *slot = s;
       return PLBM_OK;
     }
@@ -740,6 +764,8 @@ int plbm_batch_attach(plbm_batch* b, plbm_lattice* L, int32_t* slot) {
 int plbm_batch_detach(plbm_batch* b, int32_t slot) {
   if (!b || slot < 0 || slot >= b->max_slots || !b->lat[slot]) return set_error(PLBM_E_INVALID, "bad slot");
   // the lattice keeps its own time; its standalone kernel block has parity 0
+  b->lat[slot]->batch = nullptr;
+  b->lat[slot]->slot = -1;
   b->lat[slot] = nullptr;
   b->dirty = true;
   return PLBM_OK;
@@ -809,6 +835,11 @@ int plbm_batch_diag(plbm_batch* b, plbm_diag* per_slot) {
 
 void plbm_batch_destroy(plbm_batch* b) {
   if (!b) return;
+  for (int s = 0; s < b->max_slots; ++s)
+    if (b->lat[s]) {
+      b->lat[s]->batch = nullptr;
+      b->lat[s]->slot = -1;
+    }
   if (b->has_graph) (void)hipGraphExecDestroy(b->graph2);
   delete b;
 }

@@ -129,3 +129,45 @@ def test_batch_detects_an_unstable_member_without_disturbing_others():
     b.close()
     for lat in solo + mixed:
         lat.close()
+
+
+def test_batch_owns_its_lattices_until_detached():
+    """An attached lattice refuses stepping and re-initialisation through its own
+    handle and a second batch; destroying it detaches it; destroying the batch
+    releases the rest."""
+    require_gpu()
+    import torch
+    from paper_2504_15018_amd import native as N
+    fmt("batch_ownership")
+    stream = torch.cuda.Stream()
+    specs = SPECS[:3]
+    mixed = [_make(s, stream=stream) for s in specs]
+    solo = [_make(s) for s in specs]
+    b = Batch(4, 4096, stream)
+    other = Batch(2, 4096, stream)
+    slots = [b.attach(m) for m in mixed]
+    f0 = mixed[0].populations()  # reads stay allowed
+    for call in (lambda: mixed[0].step(1), lambda: mixed[0].write_populations(f0),
+                 lambda: mixed[0].init_fields(np.ones(mixed[0].N)), lambda: other.attach(mixed[0])):
+        with pytest.raises(N.PlbmError) as e:
+            call()
+        assert e.value.code == N.PLBM_E_INVALID
+    b.step(4)
+    # destroying an attached lattice frees its slot; the rest keep stepping
+    mixed[1].close()
+    b.step(3)
+    d = b.diag()
+    assert d[slots[1]].time == 0 and d[slots[1]].mass == 0.0
+    assert b.attach(solo[1]) == slots[1]  # the freed slot is reused
+    b.detach(slots[1])
+    # destroying the batch releases the lattices still attached
+    b.close()
+    other.close()
+    mixed[0].step(2)
+    for k in (0, 2):
+        steps = 9 if k == 0 else 7
+        solo[k].step(steps)
+        assert mixed[k].time == steps
+        assert np.array_equal(mixed[k].populations(), solo[k].populations()), specs[k]
+    for lat in solo + [mixed[0], mixed[2]]:
+        lat.close()
