@@ -17,6 +17,11 @@ traffic (2 Q S bytes per node update: read and write 19 float32 populations)
 over its average launch duration measured with HIP events on the lattice's
 stream; `cpu_baseline` times the FP64 NumPy oracle on a bounded sample of the
 same workload on the host.
+
+`--pattern aa` times the in-place storage pattern instead (one population
+array; a psi pass and the in-place update per step).  Its roofline covers the
+two launches of a step together: 3 Q S + 2 C bytes per node (C = 4 bytes,
+the psi value, 8 for float64) over the step's duration.
 """
 import argparse
 import json
@@ -31,7 +36,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 REDUCE_EVERY = 100
 PROFILE = os.path.join(ROOT, "profiles", "k_step_d3q19_256cubed_mrt_f32.json")
-KERNEL_SOURCES = ["plbm_device.hpp", "plbm_step.hpp", "plbm_launch.hpp", "plbm_kernels_inst.hpp", "plbm_k_f32.hip"]
+KERNEL_SOURCES = ["plbm_device.hpp", "plbm_step.hpp", "plbm_aux.hpp", "plbm_aa.hpp", "plbm_launch.hpp",
+                  "plbm_kernels_inst.hpp", "plbm_k_f32.hip"]
 
 
 def kernel_source_hash():
@@ -203,6 +209,8 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--collision", default="mrt", choices=["mrt", "bgk"])
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16s", "bf16s"])
+    ap.add_argument("--pattern", default="ab", choices=["ab", "aa"],
+                    help="population storage pattern: two arrays (ab) or in place (aa)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain device-to-device copy of 2 GiB (HBM reference for the roofline)")
@@ -238,11 +246,12 @@ def main():
     dims = (n, n, n)
     prm = N.plbm_params_pr_lattice(0.8, 0.326, 2.0, 1.0, 1.0, 1.0)
     log(f"[bench] coexistence rho_v={prm.rho_v:.6f} rho_l={prm.rho_l:.6f}")
-    lat = Lattice("D3Q19", dims, prm, collision=args.collision, storage=args.storage)
+    lat = Lattice("D3Q19", dims, prm, collision=args.collision, storage=args.storage, pattern=args.pattern)
     R = 48.0 * n / 256.0
     lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=5.0, R=R, centre=[n / 2.0] * 3)
     stream = lat.stream
-    log(f"[bench] lattice {dims} D3Q19 {args.collision} {args.storage}, {lat.nbytes / 2**30:.2f} GiB; "
+    log(f"[bench] lattice {dims} D3Q19 {args.collision} {args.storage} pattern {args.pattern}, "
+        f"{lat.nbytes / 2**30:.2f} GiB; "
         f"warmup {args.warmup}")
     lat.step(args.warmup)
     d0 = lat.reduce()
@@ -276,7 +285,10 @@ def main():
     ms_per_step = wall * 1e3 / K
     mlups = nodes * K / wall / 1e6
     S = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[args.storage]
-    bytes_per_launch = 2 * 19 * S * nodes
+    if args.pattern == "aa":  # psi pass (Q S read, C written) + in-place update (2 Q S, C of psi read)
+        bytes_per_launch = (3 * 19 * S + 2 * (8 if args.storage == "f64" else 4)) * nodes
+    else:
+        bytes_per_launch = 2 * 19 * S * nodes
     achieved = bytes_per_launch / avg_kernel_s / 1e9
     dfin = lat.reduce()
     log(f"[bench] {K} steps in {wall:.3f} s; step kernel avg {avg_kernel_s * 1e3:.4f} ms; "
@@ -286,7 +298,7 @@ def main():
         sys.exit(3)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
-    tb = profiled_traffic(args.storage, args.collision, n)
+    tb = profiled_traffic(args.storage, args.collision, n) if args.pattern == "ab" else None
     traffic = None if tb is None else round(tb / 1e9, 4)  # GB per update launch
     out = {
         "metric": "MLUPS & % HBM peak (D3Q19 P-LBM step); solves/s + p99 latency at fixed accuracy",
@@ -301,10 +313,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.storage == "f64" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"D3Q19 static droplet {n}^3 periodic, {args.storage} populations, "
+        "config": {"workload": f"D3Q19 static droplet {n}^3 periodic, {args.storage} populations"
+                               f"{' (in place)' if args.pattern == 'aa' else ''}, "
                                f"{args.collision.upper()} + Guo forcing, Peng-Robinson T/Tc=0.8, radius {R:g}, "
                                f"tanh width 5; reduction every {REDUCE_EVERY} steps",
                    "lattice": "D3Q19", "nodes": nodes, "storage": args.storage, "collision": args.collision,
+                   "pattern": args.pattern, "lattice_bytes": lat.nbytes,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},

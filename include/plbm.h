@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define PLBM_ABI_VERSION 1
+#define PLBM_ABI_VERSION 2
 
 /* status codes */
 #define PLBM_OK 0
@@ -77,6 +77,19 @@ extern "C" {
  * Extra traffic: 4 bytes per node update.  float32 arithmetic, float64 psi. */
 #define PLBM_F16R 4
 #define PLBM_BF16R 5
+/* population storage patterns */
+#define PLBM_PATTERN_AB 0 /* two population arrays; one fused kernel per step (2 Q S bytes per node) */
+/* In-place (AA) pattern: one population array.  Even steps read and write
+ * a node's own Q slots (writing each post-collision population into the
+ * opposite direction's slot); odd steps read from and write to the
+ * neighbours' slots, so each node touches only slots no other node touches
+ * and the update is in place.  The neighbours' psi cannot be read from
+ * populations that may already be overwritten, so each step is a psi pass
+ * (Q S read, one psi value written per node) and the update (2 Q S plus the
+ * psi stencil): about 1.5x the traffic of the A-B pattern for half its
+ * population memory.  Results equal those of the A-B pattern.  Not
+ * available with locally shifted storage (PLBM_F16R, PLBM_BF16R). */
+#define PLBM_PATTERN_AA 1
 /* boundary kinds, per axis */
 #define PLBM_PERIODIC 0
 #define PLBM_HALFWAY_BB 1 /* walls half a spacing outside the first and last node */
@@ -139,7 +152,7 @@ typedef struct plbm_lattice_desc {
   int32_t bc[3];      /* per axis x, y, z: PLBM_PERIODIC or PLBM_HALFWAY_BB.
                          Walls are supported on the last axis only (z in 3-D,
                          y in 2-D); other axes must be periodic. */
-  int32_t pad0;
+  int32_t pattern;    /* PLBM_PATTERN_AB | PLBM_PATTERN_AA */
   double rho0_shift;  /* reference density of shifted storage (F16S/BF16S);
                          0 selects rho_l of the parameters */
   double mrt_rates[4]; /* MRT rates s_e, s_eps, s_q, s_m; 0 selects 0.8, 0.8,
@@ -264,9 +277,10 @@ int plbm_reduce(plbm_lattice* lat, plbm_diag* out);
 void plbm_destroy(plbm_lattice* lat);
 
 /* Continuous batching.  Attached lattices may differ in size, lattice kind,
- * collision, storage and walls; those that share all four ("a type") are
- * advanced by one launch per step whose workgroups cover the tiles of every
- * such slot, so each step costs one launch per type present.  max_slots
+ * collision, storage, pattern and walls; those that share all five ("a
+ * type") are advanced by one launch per step (two for the in-place pattern)
+ * whose workgroups cover the tiles of every such slot, so each step costs
+ * one launch per type present.  max_slots
  * bounds the lattices attached at once and max_tiles their tiles together.
  * The batch owns no lattice memory; its work table lives in a caller-owned
  * device buffer of plbm_batch_bytes(max_slots, max_tiles) bytes and is

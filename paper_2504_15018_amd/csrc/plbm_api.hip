@@ -64,7 +64,7 @@ struct Layout {
   uint64_t zdata;  // bytes of node data of one z plane of stored populations
   uint64_t zblock; // zdata plus a trash area for the ragged-tile lanes of one workgroup
   int64_t N;
-  uint64_t popA, popB, refA, refB, aux, uprev, red, kp, total;
+  uint64_t popA, popB, refA, refB, psi, aux, uprev, red, kp, total;
 };
 
 bool local_shift(int storage) { return storage == PLBM_F16R || storage == PLBM_BF16R; }
@@ -108,6 +108,11 @@ int make_layout(const plbm_lattice_desc* d, Layout* L, int64_t resident = 0) {
   if (d->collision != PLBM_BGK && d->collision != PLBM_MRT) return set_error(PLBM_E_INVALID, "unknown collision");
   if (d->storage < PLBM_F64 || d->storage > PLBM_BF16R) return set_error(PLBM_E_INVALID, "unknown storage");
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) return set_error(PLBM_E_INVALID, "lattice sizes must be >= 1");
+  if (d->pattern != PLBM_PATTERN_AB && d->pattern != PLBM_PATTERN_AA)
+    return set_error(PLBM_E_INVALID, "unknown storage pattern");
+  const bool aa = d->pattern == PLBM_PATTERN_AA;
+  if (aa && local_shift(d->storage))
+    return set_error(PLBM_E_UNSUPPORTED, "the in-place pattern has no locally shifted storage form");
   const bool is2d = d->lattice == PLBM_D2Q9;
   if (is2d && d->nz != 1) return set_error(PLBM_E_INVALID, "D2Q9 requires nz = 1");
   for (int a = 0; a < 3; ++a)
@@ -153,8 +158,12 @@ int make_layout(const plbm_lattice_desc* d, Layout* L, int64_t resident = 0) {
   uint64_t off = 0;
   L->popA = off;
   off = align_up(off + L->zblock * L->nzk);
-  L->popB = off;
-  off = align_up(off + L->zblock * L->nzk);
+  L->popB = aa ? L->popA : off;  // the in-place pattern has one array
+  if (!aa) off = align_up(off + L->zblock * L->nzk);
+  // in-place pattern: psi of every node in the arithmetic type (float64 for
+  // float64 storage, float32 otherwise)
+  L->psi = off;
+  if (aa) off = align_up(off + (uint64_t)L->N * (d->storage == PLBM_F64 ? 8 : 4));
   // reference densities of locally shifted storage: N nodes + a trash slot per thread
   const uint64_t nref = local_shift(d->storage) ? (uint64_t)(L->N + 256) * 2 : 0;
   L->refA = off;
@@ -220,15 +229,16 @@ int64_t resident_workgroups(const plbm_lattice_desc& d) {
   const int lat = d.lattice == PLBM_D3Q19 ? 1 : 0;
   const int last = lat ? 2 : 1;
   const int walls = d.bc[last] == PLBM_HALFWAY_BB;
+  const int aa = d.pattern == PLBM_PATTERN_AA;
   int blocks = 0, dev = 0, cus = 0;
   hipError_t e;
   switch (d.storage) {
-    case PLBM_F64: e = occupancy_step_f64(lat, d.collision, walls, &blocks); break;
-    case PLBM_F32: e = occupancy_step_f32(lat, d.collision, walls, &blocks); break;
-    case PLBM_F16S: e = occupancy_step_f16s(lat, d.collision, walls, &blocks); break;
-    case PLBM_BF16S: e = occupancy_step_bf16s(lat, d.collision, walls, &blocks); break;
-    case PLBM_F16R: e = occupancy_step_f16r(lat, d.collision, walls, &blocks); break;
-    default: e = occupancy_step_bf16r(lat, d.collision, walls, &blocks); break;
+    case PLBM_F64: e = occupancy_step_f64(lat, d.collision, walls, aa, &blocks); break;
+    case PLBM_F32: e = occupancy_step_f32(lat, d.collision, walls, aa, &blocks); break;
+    case PLBM_F16S: e = occupancy_step_f16s(lat, d.collision, walls, aa, &blocks); break;
+    case PLBM_BF16S: e = occupancy_step_bf16s(lat, d.collision, walls, aa, &blocks); break;
+    case PLBM_F16R: e = occupancy_step_f16r(lat, d.collision, walls, aa, &blocks); break;
+    default: e = occupancy_step_bf16r(lat, d.collision, walls, aa, &blocks); break;
   }
   if (e != hipSuccess || blocks <= 0) return 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -258,6 +268,7 @@ int run_step_kernel(plbm_lattice* L, int mode, int phase, double* orho, double* 
   a.coll = L->desc.collision;
   a.mode = mode;
   a.walls = L->kp.bb_z;
+  a.aa = L->kp.aa;
   a.nblocks = L->lay.ntiles;
   a.stream = L->stream;
   a.P = L->kp_dev;
@@ -299,6 +310,8 @@ void fill_kparams(plbm_lattice* L) {
   k.pop[1] = L->mem + y.popB;
   k.ref[0] = local_shift(L->desc.storage) ? L->mem + y.refA : nullptr;
   k.ref[1] = local_shift(L->desc.storage) ? L->mem + y.refB : nullptr;
+  k.aa = L->desc.pattern == PLBM_PATTERN_AA;
+  k.psi = k.aa ? L->mem + y.psi : nullptr;
   k.aux = reinterpret_cast<double*>(L->mem + y.aux);
   k.uprev = reinterpret_cast<float*>(L->mem + y.uprev);
   k.red = reinterpret_cast<double*>(L->mem + y.red);
@@ -618,7 +631,7 @@ struct plbm_batch {
   WorkItem* work_dev;
   std::vector<plbm_lattice*> lat;
   struct Group {
-    int lattice, coll, storage, walls;
+    int lattice, coll, storage, walls, aa;
     int offset, count;  // segment of the work table
   };
   std::vector<Group> groups;
@@ -656,14 +669,14 @@ int batch_rebuild(plbm_batch* b) {
   }
   b->groups.clear();
   b->work_host.clear();
-  std::map<std::tuple<int, int, int, int>, std::vector<int>> by_type;
+  std::map<std::tuple<int, int, int, int, int>, std::vector<int>> by_type;
   for (int s = 0; s < b->max_slots; ++s) {
     plbm_lattice* L = b->lat[s];
     if (!L) continue;
     KParams k = L->kp;
     k.parity = (int)(L->t & 1);
     b->slots_host[s] = k;
-    by_type[std::make_tuple(L->desc.lattice, L->desc.collision, L->desc.storage, L->kp.bb_z)].push_back(s);
+    by_type[std::make_tuple(L->desc.lattice, L->desc.collision, L->desc.storage, L->kp.bb_z, L->kp.aa)].push_back(s);
   }
   for (auto& kv : by_type) {
     plbm_batch::Group gr;
@@ -671,6 +684,7 @@ int batch_rebuild(plbm_batch* b) {
     gr.coll = std::get<1>(kv.first);
     gr.storage = std::get<2>(kv.first);
     gr.walls = std::get<3>(kv.first);
+    gr.aa = std::get<4>(kv.first);
     gr.offset = (int)b->work_host.size();
     for (int s : kv.second)
       for (int t = 0; t < b->lat[s]->lay.ntiles; ++t) b->work_host.push_back(WorkItem{s, t});
@@ -698,6 +712,7 @@ int batch_launch(plbm_batch* b, int mode, int phase) {
     a.coll = gr.coll;
     a.mode = mode;
     a.walls = gr.walls;
+    a.aa = gr.aa;
     a.nblocks = gr.count;
     a.stream = b->stream;
     a.P = b->slots_dev;

@@ -6,16 +6,27 @@
 
 namespace plbm {
 
-// Storage index (in elements of T) of f_i(x) of the post-streaming state.
-// Populations are kept post-collision: f_i(x) lives at A_i(x - c_i), or at
-// A_opp(i)(x) when x - c_i lies beyond a half-way bounce-back wall.
+// Storage index (in elements of T) of f_i(x) of the post-streaming state at
+// time parity par.  A-B pattern: populations are kept post-collision, f_i(x)
+// lives at A_i(x - c_i), or at A_opp(i)(x) when x - c_i lies beyond a
+// half-way bounce-back wall.  In-place pattern: at even time f_i(x) lives at
+// A_i(x); at odd time at A_opp(i)(x - c_i), or at A_i(x) beyond a wall.
 template <class L, class T>
-__device__ __forceinline__ int64_t storage_index(const KParams& p, int i, int x, int y, int z) {
+__device__ __forceinline__ int64_t storage_index(const KParams& p, int par, int i, int x, int y, int z) {
   constexpr int XB = Lines<T>::XB;
   constexpr int QS = Lines<T>::template slots<L::Q>();
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   int sz = z - L::cz[i], sx = x - L::cx[i], sy = y - L::cy[i], q = i;
-  if (p.bb_z && (sz < 0 || sz >= nz)) {
+  const bool wall = p.bb_z && (sz < 0 || sz >= nz);
+  if (p.aa) {
+    if (par == 0 || wall) {
+      sx = x;
+      sy = y;
+      sz = z;
+    } else {
+      q = L::opp[i];
+    }
+  } else if (wall) {
     sx = x;
     sy = y;
     sz = z;
@@ -28,11 +39,14 @@ __device__ __forceinline__ int64_t storage_index(const KParams& p, int i, int x,
   return (int64_t)sz * (p.zblock / (int64_t)sizeof(T)) + (((int64_t)sy * p.nxb + sx / XB) * QS + q) * XB + sx % XB;
 }
 
-// Direction whose storage slot holds f_i(x) (differs from i only at walls).
+// Direction whose storage slot holds f_i(x) (the weight of the shift of a
+// shifted storage; opposite directions have equal weights).
 template <class L>
-__device__ __forceinline__ int storage_dir(const KParams& p, int i, int z) {
+__device__ __forceinline__ int storage_dir(const KParams& p, int par, int i, int z) {
   const int sz = z - L::cz[i];
-  return (p.bb_z && (sz < 0 || sz >= p.nz)) ? L::opp[i] : i;
+  const bool wall = p.bb_z && (sz < 0 || sz >= p.nz);
+  if (p.aa) return (par == 0 || wall) ? i : L::opp[i];
+  return wall ? L::opp[i] : i;
 }
 
 // Second-order equilibrium of eq. (Single_Phase_EDF), float64.
@@ -63,8 +77,8 @@ __device__ __forceinline__ void write_equilibrium(const KParams& p, int par, int
   const double rs = shift_density<St>(p, par, n);
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
-    const int dir = storage_dir<L>(p, i, z);
-    A[storage_index<L, typename St::T>(p, i, x, y, z)] = St::enc64(feq64<L>(i, rho, u), L::w[dir] * rs);
+    const int dir = storage_dir<L>(p, par, i, z);
+    A[storage_index<L, typename St::T>(p, par, i, x, y, z)] = St::enc64(feq64<L>(i, rho, u), L::w[dir] * rs);
   }
 }
 
@@ -134,8 +148,8 @@ __global__ __launch_bounds__(256) void k_read_pop(const KParams* __restrict__ P,
   for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < p.N; n += (int64_t)gridDim.x * blockDim.x) {
     int x, y, z;
     node_xyz(p, n, &x, &y, &z);
-    const int dir = storage_dir<L>(p, dirq, z);
-    out[n] = St::dec64(A[storage_index<L, typename St::T>(p, dirq, x, y, z)], L::w[dir] * shift_density<St>(p, par, n));
+    const int dir = storage_dir<L>(p, par, dirq, z);
+    out[n] = St::dec64(A[storage_index<L, typename St::T>(p, par, dirq, x, y, z)], L::w[dir] * shift_density<St>(p, par, n));
   }
 }
 
@@ -148,8 +162,8 @@ __global__ __launch_bounds__(256) void k_write_pop(const KParams* __restrict__ P
   for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < p.N; n += (int64_t)gridDim.x * blockDim.x) {
     int x, y, z;
     node_xyz(p, n, &x, &y, &z);
-    const int dir = storage_dir<L>(p, dirq, z);
-    A[storage_index<L, typename St::T>(p, dirq, x, y, z)] = St::enc64(in[n], L::w[dir] * shift_density<St>(p, par, n));
+    const int dir = storage_dir<L>(p, par, dirq, z);
+    A[storage_index<L, typename St::T>(p, par, dirq, x, y, z)] = St::enc64(in[n], L::w[dir] * shift_density<St>(p, par, n));
   }
 }
 

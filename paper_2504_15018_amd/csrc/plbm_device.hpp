@@ -207,8 +207,9 @@ using RefT = _Float16;
 enum : int32_t { EOS_PAPER = 0, EOS_PR = 1 };
 
 struct KParams {
-  void* pop[2];       // A-B population arrays, each Q*N entries
+  void* pop[2];       // A-B population arrays, each Q*N entries (in-place pattern: both the one array)
   void* ref[2];       // locally shifted storage: A-B reference densities, N + 256 half values
+  void* psi;          // in-place pattern: psi of every node at the current time (arithmetic type)
   double* aux;        // float64 staging, 4*N
   float* uprev;       // previous velocity for the residual, D*N
   double* red;        // reduction partials
@@ -227,7 +228,8 @@ struct KParams {
   double Fg[3];
   double rates[4];                 // s_e, s_eps, s_q, s_m
   double rho0_shift;
-  int32_t parity;  // batch slots: A-B phase offset of this lattice
+  int32_t parity;  // batch slots: phase offset of this lattice (its time parity)
+  int32_t aa;      // in-place (AA) pattern
   int32_t nxb;     // x blocks of one 128-byte line per row (storage layout)
   int64_t zblock;  // bytes of one z plane of stored populations (node data + trash)
   int64_t zdata;   // bytes of the node data of one z plane

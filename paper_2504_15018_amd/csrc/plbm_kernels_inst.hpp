@@ -1,5 +1,6 @@
 // Instantiation of every kernel for one storage type.  Included by the
 // per-storage translation units with PLBM_ST (codec) and PLBM_SUFFIX defined.
+#include "plbm_aa.hpp"
 #include "plbm_aux.hpp"
 #include "plbm_launch.hpp"
 
@@ -12,9 +13,26 @@ namespace plbm {
 #define PLBM_LDS_PAD 0  // extra LDS bytes per workgroup (limits workgroups per CU)
 #endif
 
+// In-place pattern: the psi pass, then the update (locally shifted storage
+// has no in-place form).
+template <class L, int COLL, int MODE, bool WALLS>
+static hipError_t go_aa(const StepLaunch& a) {
+  using TS = TileShape<L>;
+  if constexpr (PLBM_ST::local) {
+    return hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((k_aa_psi<L, PLBM_ST, TS::TX, TS::TY, WALLS>), dim3(a.nblocks * PSI_SPLIT), dim3(TS::TX * TS::TY), 0,
+                       a.stream, a.P, a.work, a.nwork, a.phase);
+    hipLaunchKernelGGL((k_aa_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, WALLS>), dim3(a.nblocks),
+                       dim3(TS::TX * TS::TY), 0, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
+    return hipGetLastError();
+  }
+}
+
 template <class L, int COLL, int MODE>
 static hipError_t go_step(const StepLaunch& a) {
   using TS = TileShape<L>;
+  if (a.aa) return a.walls ? go_aa<L, COLL, MODE, true>(a) : go_aa<L, COLL, MODE, false>(a);
   if (a.walls)
     hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, TS::NT, true>), dim3(a.nblocks), dim3(TS::NT),
                        PLBM_LDS_PAD, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
@@ -36,16 +54,21 @@ hipError_t PLBM_CAT(launch_step_, PLBM_SUFFIX)(const StepLaunch& a) {
 }
 
 template <class L, int COLL, bool WALLS>
-static hipError_t occ_go(int* blocks) {
+static hipError_t occ_go(int aa, int* blocks) {
   using TS = TileShape<L>;
+  if constexpr (!PLBM_ST::local) {
+    if (aa)
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          blocks, k_aa_step<L, PLBM_ST, COLL, MODE_STEP, TS::TX, TS::TY, WALLS>, TS::TX * TS::TY, 0);
+  }
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
       blocks, k_step<L, PLBM_ST, COLL, MODE_STEP, TS::TX, TS::TY, TS::NT, WALLS>, TS::NT, PLBM_LDS_PAD);
 }
 
 template <class L>
-static hipError_t occ_for(int coll, int walls, int* blocks) {
-  if (coll == COLL_MRT) return walls ? occ_go<L, COLL_MRT, true>(blocks) : occ_go<L, COLL_MRT, false>(blocks);
-  return walls ? occ_go<L, COLL_BGK, true>(blocks) : occ_go<L, COLL_BGK, false>(blocks);
+static hipError_t occ_for(int coll, int walls, int aa, int* blocks) {
+  if (coll == COLL_MRT) return walls ? occ_go<L, COLL_MRT, true>(aa, blocks) : occ_go<L, COLL_MRT, false>(aa, blocks);
+  return walls ? occ_go<L, COLL_BGK, true>(aa, blocks) : occ_go<L, COLL_BGK, false>(aa, blocks);
 }
 
 void PLBM_CAT(tile_shape_, PLBM_SUFFIX)(int* tx, int* ty) {
@@ -53,8 +76,8 @@ void PLBM_CAT(tile_shape_, PLBM_SUFFIX)(int* tx, int* ty) {
   *ty = TileShape<D3Q19L>::TY;
 }
 
-hipError_t PLBM_CAT(occupancy_step_, PLBM_SUFFIX)(int lattice, int coll, int walls, int* blocks) {
-  return lattice == 1 ? occ_for<D3Q19L>(coll, walls, blocks) : occ_for<D2Q9L>(coll, walls, blocks);
+hipError_t PLBM_CAT(occupancy_step_, PLBM_SUFFIX)(int lattice, int coll, int walls, int aa, int* blocks) {
+  return lattice == 1 ? occ_for<D3Q19L>(coll, walls, aa, blocks) : occ_for<D2Q9L>(coll, walls, aa, blocks);
 }
 
 template <class L>

@@ -46,6 +46,7 @@ struct StepLaunch {
   int coll;     // 0 BGK, 1 MRT
   int mode;     // 0 step, 1 moments, 2 reduce
   int walls;    // half-way bounce-back on the marching axis
+  int aa;       // in-place pattern: psi pass, then the in-place update
   int nblocks;
   hipStream_t stream;
   const KParams* P;
@@ -93,12 +94,12 @@ void tile_shape_bf16s(int* tx, int* ty);
 void tile_shape_f16r(int* tx, int* ty);
 void tile_shape_bf16r(int* tx, int* ty);
 // resident workgroups per CU of the update kernel (hipOccupancy...)
-hipError_t occupancy_step_f64(int lattice, int coll, int walls, int* blocks);
-hipError_t occupancy_step_f32(int lattice, int coll, int walls, int* blocks);
-hipError_t occupancy_step_f16s(int lattice, int coll, int walls, int* blocks);
-hipError_t occupancy_step_bf16s(int lattice, int coll, int walls, int* blocks);
-hipError_t occupancy_step_f16r(int lattice, int coll, int walls, int* blocks);
-hipError_t occupancy_step_bf16r(int lattice, int coll, int walls, int* blocks);
+hipError_t occupancy_step_f64(int lattice, int coll, int walls, int aa, int* blocks);
+hipError_t occupancy_step_f32(int lattice, int coll, int walls, int aa, int* blocks);
+hipError_t occupancy_step_f16s(int lattice, int coll, int walls, int aa, int* blocks);
+hipError_t occupancy_step_bf16s(int lattice, int coll, int walls, int aa, int* blocks);
+hipError_t occupancy_step_f16r(int lattice, int coll, int walls, int aa, int* blocks);
+hipError_t occupancy_step_bf16r(int lattice, int coll, int walls, int aa, int* blocks);
 hipError_t launch_accum(hipStream_t st, int nblocks, int64_t N, int first, const double* in, double* acc);
 hipError_t launch_set_ref(hipStream_t st, int nblocks, const KParams* P, int par, const double* acc);
 hipError_t launch_reduce_final(hipStream_t st, const KParams* P, int ntiles, void* out);

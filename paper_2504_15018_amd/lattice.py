@@ -12,11 +12,14 @@ LATTICE = {"D2Q9": N.PLBM_D2Q9, "D3Q19": N.PLBM_D3Q19}
 COLLISION = {"bgk": N.PLBM_BGK, "mrt": N.PLBM_MRT}
 STORAGE = {"f64": N.PLBM_F64, "f32": N.PLBM_F32, "f16s": N.PLBM_F16S, "bf16s": N.PLBM_BF16S,
            "f16r": N.PLBM_F16R, "bf16r": N.PLBM_BF16R}
+PATTERN = {"ab": N.PLBM_PATTERN_AB, "aa": N.PLBM_PATTERN_AA}
 Q_OF = {"D2Q9": 9, "D3Q19": 19}
 
 
-def make_desc(lattice, dims, collision="bgk", storage="f64", walls=False, rho0_shift=0.0, mrt_rates=None):
-    """dims = (nx, ny) for D2Q9 or (nx, ny, nz) for D3Q19; walls on the last axis."""
+def make_desc(lattice, dims, collision="bgk", storage="f64", walls=False, rho0_shift=0.0, mrt_rates=None,
+              pattern="ab"):
+    """dims = (nx, ny) for D2Q9 or (nx, ny, nz) for D3Q19; walls on the last axis;
+    pattern "ab" (two population arrays) or "aa" (in place)."""
     d = N.plbm_lattice_desc()
     d.lattice = LATTICE[lattice]
     d.collision = COLLISION[collision]
@@ -27,6 +30,7 @@ def make_desc(lattice, dims, collision="bgk", storage="f64", walls=False, rho0_s
     last = len(dims) - 1
     for a in range(3):
         d.bc[a] = N.PLBM_HALFWAY_BB if (walls and a == last) else N.PLBM_PERIODIC
+    d.pattern = PATTERN[pattern]
     d.rho0_shift = rho0_shift
     for k, v in enumerate(mrt_rates or (0.0, 0.0, 0.0, 0.0)):
         d.mrt_rates[k] = v
@@ -35,7 +39,7 @@ def make_desc(lattice, dims, collision="bgk", storage="f64", walls=False, rho0_s
 
 class Lattice:
     def __init__(self, lattice, dims, params, collision="bgk", storage="f64", walls=False, rho0_shift=0.0,
-                 mrt_rates=None, stream=None, device="cuda"):
+                 mrt_rates=None, stream=None, device="cuda", pattern="ab"):
         import torch
 
         self.name = lattice
@@ -44,7 +48,7 @@ class Lattice:
         self.Q = Q_OF[lattice]
         self.N = int(np.prod(self.dims))
         self.shape = tuple(reversed(self.dims))
-        self.desc = make_desc(lattice, dims, collision, storage, walls, rho0_shift, mrt_rates)
+        self.desc = make_desc(lattice, dims, collision, storage, walls, rho0_shift, mrt_rates, pattern)
         self.params = params
         self.nbytes = N.plbm_lattice_bytes(self.desc)
         self.mem = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)

@@ -78,7 +78,8 @@ def from_synth(reqs):
 
 class Server:
     def __init__(self, budget_bytes, max_slots=64, max_tiles=1 << 20, check_every=100, tol=1e-8,
-                 max_steps=2_000_000, storage="f32", collision="bgk", keep_lattices=False, width=5.0):
+                 max_steps=2_000_000, storage="f32", collision="bgk", keep_lattices=False, width=5.0,
+                 pattern="ab"):
         import torch
 
         self.torch = torch
@@ -89,6 +90,7 @@ class Server:
         self.max_steps = int(max_steps)
         self.storage = storage
         self.collision = collision
+        self.pattern = pattern  # "aa": in place, about half the population memory per resident lattice
         self.keep = keep_lattices
         self.width = width
         self.stream = torch.cuda.Stream()
@@ -112,12 +114,13 @@ class Server:
     # ---- admission ----
     def _desc_bytes(self, req):
         from .lattice import make_desc
-        return N.plbm_lattice_bytes(make_desc(req.lattice, req.dims, self.collision, self.storage)) + 256
+        return N.plbm_lattice_bytes(make_desc(req.lattice, req.dims, self.collision, self.storage,
+                                              pattern=self.pattern)) + 256
 
     def _admit(self, req, now):
         req.params = N.plbm_params_pr_lattice(req.T_over_Tc, 0.326, 2.0, 1.0, 1.0, 1.0)
         lat = Lattice(req.lattice, req.dims, req.params, collision=self.collision, storage=self.storage,
-                      stream=self.stream)
+                      stream=self.stream, pattern=self.pattern)
         req.lat = lat
         centre = [n / 2.0 for n in req.dims]
         lat.init_shape(N.PLBM_SHAPE_DROPLET, req.params.rho_l, req.params.rho_v, W=self.width, R=req.radius,

@@ -151,6 +151,28 @@ def test_lattice_bytes_and_validation():
     assert ei.value.code == N.PLBM_E_UNSUPPORTED
 
 
+def test_inplace_pattern_bytes_and_validation():
+    """The in-place pattern holds one population array plus a psi array."""
+    from paper_2504_15018_amd.lattice import make_desc
+    n = 64 * 48 * 40
+    for st, S, C in (("f32", 4, 4), ("f64", 8, 8), ("bf16s", 2, 4)):
+        ab = N.plbm_lattice_bytes(make_desc("D3Q19", (64, 48, 40), storage=st))
+        aa = N.plbm_lattice_bytes(make_desc("D3Q19", (64, 48, 40), storage=st, pattern="aa"))
+        saved = ab - aa
+        # one population array less (with a trash area of at most 40 KiB per
+        # z plane for ragged-tile lanes), one psi array more
+        assert 19 * n * S - n * C <= saved <= 19 * n * S - n * C + 40 * 40 * 1024 + (1 << 20)
+    for st in ("f16r", "bf16r"):
+        with pytest.raises(N.PlbmError) as ei:
+            N.plbm_lattice_bytes(make_desc("D3Q19", (16, 16, 16), storage=st, pattern="aa"))
+        assert ei.value.code == N.PLBM_E_UNSUPPORTED
+    bad = make_desc("D2Q9", (8, 8))
+    bad.pattern = 7
+    with pytest.raises(N.PlbmError) as ei:
+        N.plbm_lattice_bytes(bad)
+    assert ei.value.code == N.PLBM_E_INVALID
+
+
 def test_create_rejects_small_buffer_before_touching_the_device():
     from paper_2504_15018_amd.lattice import make_desc
     d = make_desc("D2Q9", (16, 16))

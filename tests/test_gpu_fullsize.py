@@ -61,9 +61,10 @@ def _window_parity(lat, op, rho_fn, u0, dims, storage, steps, windows, out_size)
     return f_gpu
 
 
-@pytest.mark.parametrize("variant", ["static", "galilean"])
+@pytest.mark.parametrize("variant", ["static", "galilean", "static-inplace"])
 def test_c3_droplet_256cubed_f32_mrt_windows(variant):
-    """D3Q19 256^3, float32 MRT + Guo, PR T/Tc = 0.8, droplet R = 48 (W = 5); Galilean variant u0 = 0.05 x."""
+    """D3Q19 256^3, float32 MRT + Guo, PR T/Tc = 0.8, droplet R = 48 (W = 5); Galilean variant u0 = 0.05 x;
+    the in-place pattern over an odd step count (ends in the odd-time layout)."""
     require_gpu()
     from paper_2504_15018_amd.lattice import Lattice
     fmt("c3_fullsize", variant=variant)
@@ -80,10 +81,11 @@ def test_c3_droplet_256cubed_f32_mrt_windows(variant):
     del co
     u_full = np.zeros((3,) + rho_full.shape)
     u_full[0] = u0[0]
-    lat = Lattice("D3Q19", dims, lib_params(), collision="mrt", storage="f32")
+    inplace = variant.endswith("inplace")
+    lat = Lattice("D3Q19", dims, lib_params(), collision="mrt", storage="f32", pattern="aa" if inplace else "ab")
     lat.init_fields(rho_full, u_full)
     del u_full
-    steps = 8
+    steps = 9 if inplace else 8
     lat.step(steps)
     windows = [(172, 124, 124), (124, 124, 124), (252, 250, 251), (100, 170, 30)]
     _window_parity(lat, op, rho_fn, u0, dims, "f32", steps, windows, 8)

@@ -1,0 +1,152 @@
+"""In-place (AA-pattern) storage on the GPU.
+
+* Against the FP64 oracle, on the same bars as the A-B parity tests
+  (float64: 1e-12 relative on f and rho, 1e-12 absolute on u; float32:
+  2e-6 / 1e-6 per step), at sizes spanning several tiles with ragged tails,
+  with and without walls, for even and odd step counts.
+* Against the A-B pattern: the two patterns run the same density sum, psi,
+  force and collision arithmetic on the same values, so populations, moments
+  and reductions must agree bitwise after any number of steps (both time
+  parities, the graph path for n >= 8) and in every storage type that has an
+  in-place form.
+* In a continuous batch mixed with A-B lattices: bitwise equal to solo runs.
+"""
+import numpy as np
+import pytest
+
+from oracle import step as S
+
+from gpu_cases import abs_max, fmt, lib_params, oracle_params, random_state, rel_max, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+ORACLE_CASES = [
+    # lattice, dims, collision, storage, walls, steps, extra
+    ("D2Q9", (37, 29), "bgk", "f64", False, 5, {}),
+    ("D2Q9", (150, 21), "mrt", "f64", True, 6, {"tau_v": 0.8, "tau_l": 1.3, "Fg": (2e-5, -1e-5)}),
+    ("D3Q19", (37, 21, 13), "bgk", "f64", False, 4, {}),
+    ("D3Q19", (70, 18, 11), "mrt", "f64", True, 3, {"tau_v": 0.8, "tau_l": 1.2, "Fg": (1e-5, 2e-6, -3e-6)}),
+    ("D3Q19", (35, 17, 10), "mrt", "f32", False, 3, {}),
+    ("D3Q19", (66, 12, 12), "bgk", "f32", True, 4, {"Fg": (1e-5, 0.0, 0.0)}),
+]
+
+
+def _ids(c):
+    return f"{c[0]}-{'x'.join(map(str, c[1]))}-{c[2]}-{c[3]}-{'bb' if c[4] else 'per'}-{c[5]}"
+
+
+@pytest.mark.parametrize("case", ORACLE_CASES, ids=_ids)
+def test_inplace_matches_the_oracle(case):
+    require_gpu()
+    from paper_2504_15018_amd.lattice import Lattice
+    lattice, dims, collision, storage, walls, steps, extra = case
+    fmt("inplace_oracle", case=_ids(case))
+    f0 = random_state(lattice, dims, 11)
+    op = oracle_params(lattice, collision=collision, walls=walls, **extra)
+    lat = Lattice(lattice, dims, lib_params(**extra), collision=collision, storage=storage, walls=walls,
+                  pattern="aa")
+    lat.write_populations(f0)
+    if storage == "f32":
+        f0 = f0.astype(np.float32).astype(np.float64)
+    assert np.array_equal(lat.populations(), f0)  # the canonical read-back of the even-parity layout
+    lat.step(steps)
+    f_ref = S.run(op, f0, steps)
+    tf, tu = (1e-12, 1e-12) if storage == "f64" else (2e-6 * steps, 1e-6 * steps)
+    assert rel_max(lat.populations(), f_ref) <= tf
+    rho, u = lat.moments()
+    rho_ref, u_ref = S.moments(op, f_ref)
+    assert rel_max(rho, rho_ref) <= tf
+    assert abs_max(u, u_ref) <= tu
+    lat.close()
+
+
+BITWISE = [
+    # lattice, dims, collision, storage, walls
+    ("D3Q19", (70, 19, 13), "mrt", "f64", True),
+    ("D3Q19", (40, 24, 9), "bgk", "f64", False),
+    ("D2Q9", (150, 33), "mrt", "f64", False),
+    ("D3Q19", (70, 19, 13), "mrt", "f32", True),
+    ("D3Q19", (33, 17, 12), "mrt", "f32", False),
+    ("D2Q9", (131, 40), "bgk", "f32", True),
+    ("D3Q19", (36, 18, 12), "mrt", "f16s", True),
+    ("D3Q19", (40, 20, 10), "bgk", "bf16s", False),
+    ("D2Q9", (96, 40), "mrt", "bf16s", True),
+]
+
+
+@pytest.mark.parametrize("spec", BITWISE, ids=lambda c: f"{c[0]}-{'x'.join(map(str, c[1]))}-{c[2]}-{c[3]}-{c[4]}")
+def test_inplace_equals_ab_bitwise(spec):
+    """Odd and even step counts, graph and direct launches, moments and reductions."""
+    require_gpu()
+    from paper_2504_15018_amd.lattice import Lattice
+    lattice, dims, collision, storage, walls = spec
+    fmt("inplace_vs_ab", spec=spec)
+    prm = lib_params(tau_v=0.9, tau_l=1.1, Fg=(1e-5, 0.0, -2e-6))
+    f0 = random_state(lattice, dims, 5)
+    ab = Lattice(lattice, dims, prm, collision=collision, storage=storage, walls=walls)
+    aa = Lattice(lattice, dims, prm, collision=collision, storage=storage, walls=walls, pattern="aa")
+    ab.write_populations(f0)
+    aa.write_populations(f0)
+    assert np.array_equal(ab.populations(), aa.populations())
+    for n in (1, 2, 9, 8, 3):  # total 23: both parities before and after graph runs
+        ab.step(n)
+        aa.step(n)
+        assert aa.time == ab.time
+        assert np.array_equal(ab.populations(), aa.populations()), (n, ab.time)
+        r1, u1 = ab.moments()
+        r2, u2 = aa.moments()
+        assert np.array_equal(r1, r2) and np.array_equal(u1, u2)
+        d1, d2 = ab.reduce(), aa.reduce()
+        assert d1.mass == d2.mass and d1.max_u == d2.max_u and list(d1.momentum) == list(d2.momentum)
+        assert d1.flags == d2.flags
+    # writing populations at odd time goes through the odd-parity layout
+    f1 = ab.populations()
+    f1[0] *= 1.0 + 1e-3
+    ab.write_populations(f1)
+    aa.write_populations(f1)
+    ab.step(3)
+    aa.step(3)
+    assert np.array_equal(ab.populations(), aa.populations())
+    ab.close()
+    aa.close()
+
+
+def test_inplace_in_a_batch_matches_solo_bitwise():
+    require_gpu()
+    import torch
+    from paper_2504_15018_amd.lattice import Lattice
+    from test_gpu_batch import Batch
+    fmt("inplace_batch")
+    specs = [
+        ("D3Q19", (40, 24, 18), "mrt", "f32", False, "aa"),
+        ("D3Q19", (40, 24, 18), "mrt", "f32", False, "ab"),
+        ("D3Q19", (33, 17, 12), "bgk", "f64", True, "aa"),
+        ("D2Q9", (150, 40), "bgk", "f32", False, "aa"),
+    ]
+    prm = lib_params(tau_v=0.9, tau_l=1.1)
+
+    def make(k, s, stream=None):
+        lat = Lattice(s[0], s[1], prm, collision=s[2], storage=s[3], walls=s[4], pattern=s[5], stream=stream)
+        lat.write_populations(random_state(s[0], s[1], 20 + k))
+        return lat
+
+    stream = torch.cuda.Stream()
+    solo = [make(k, s) for k, s in enumerate(specs)]
+    mixed = [make(k, s, stream) for k, s in enumerate(specs)]
+    mixed[2].step(1)  # an odd-time member: its parity offset is carried by the batch
+    solo[2].step(1)
+    b = Batch(6, 4096, stream)
+    slots = [b.attach(m) for m in mixed]
+    b.step(9)
+    b.step(2)
+    stream.synchronize()
+    d = b.diag()
+    for k, lat in enumerate(solo):
+        lat.step(11)
+        assert mixed[k].time == lat.time
+        assert np.array_equal(mixed[k].populations(), lat.populations()), specs[k]
+        ref = lat.reduce()
+        assert d[slots[k]].mass == ref.mass and d[slots[k]].max_u == ref.max_u
+    b.close()
+    for lat in solo + mixed:
+        lat.close()

@@ -9,18 +9,20 @@ from gpu_cases import fmt, require_gpu
 pytestmark = pytest.mark.gpu
 
 
-def test_serving_small_stream_matches_solo_runs():
+@pytest.mark.parametrize("pattern", ["ab", "aa"])
+def test_serving_small_stream_matches_solo_runs(pattern):
+    """Served in place or not, every result equals a solo A-B run bitwise."""
     require_gpu()
     import plbm_synth as syn
     from paper_2504_15018_amd import native as N
     from paper_2504_15018_amd.lattice import Lattice
     from paper_2504_15018_amd.serving import Server, from_synth
 
-    fmt("serving_small_stream")
+    fmt("serving_small_stream", pattern=pattern)
     reqs = from_synth(syn.request_stream(10, 200.0, seed=3, side2d=(24, 72), side3d=(12, 24), t_range=(0.75, 0.9)))
     big = max(reqs, key=lambda r: r.nodes)
     srv = Server(budget_bytes=0, max_slots=4, max_tiles=4096, check_every=50, tol=1e-6, max_steps=6000,
-                 keep_lattices=True)
+                 keep_lattices=True, pattern=pattern)
     # budget: room for the largest request and a bit more, so later arrivals queue behind running ones
     sizes = [srv._desc_bytes(r) for r in reqs]
     srv.budget = int(max(sizes) * 1.5)
