@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define PLBM_ABI_VERSION 2
+#define PLBM_ABI_VERSION 3
 
 /* status codes */
 #define PLBM_OK 0
@@ -158,6 +158,13 @@ typedef struct plbm_lattice_desc {
   double mrt_rates[4]; /* MRT rates s_e, s_eps, s_q, s_m; 0 selects 0.8, 0.8,
                           1.1, 1.1.  Stress (and D3Q19 pi) moments relax at
                           1/tau(rho); momentum moments are rate-independent. */
+  double rho_wall[2];  /* wetting walls (an extension beyond the paper's solid
+                          walls): the psi ghost beyond the wall below / above
+                          is psi(rho_wall) instead of the mirror of the
+                          wall-adjacent node, which sets the contact angle
+                          (rho_wall near rho_l wets, near rho_v does not).
+                          0 keeps the neutral mirror ghost.  Requires walls;
+                          must be finite and >= 0. */
 } plbm_lattice_desc;
 
 /* Initial density shape evaluated on the device (tanh interfaces of width W,

@@ -258,12 +258,25 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
     if (zl >= nz) return WALLS ? nz - 1 : zl - nz;
     return zl;
   };
+  // wetting walls: psi(rho_w) on the ghost plane instead of the mirror
+  const bool wet_lo = WALLS && kp->rho_wall[0] > 0.0, wet_hi = WALLS && kp->rho_wall[1] > 0.0;
+  C psw_lo = 0, psw_hi = 0;
+  if (wet_lo) {
+    bool d_;
+    psw_lo = psi_eval<C>(eos, kp->rho_wall[0], &d_);
+  }
+  if (wet_hi) {
+    bool d_;
+    psw_hi = psi_eval<C>(eos, kp->rho_wall[1], &d_);
+  }
   auto stage_psi = [&](int zl) {
     const C* src = psi + (uint32_t)wrapz(zl) * plane;
     C* sl = lds_psi + ((zl - z0 + 1) & 3) * PL;
+    const bool ghost = WALLS && ((zl < 0 && wet_lo) || (zl >= nz && wet_hi));
+    const C gv = zl < 0 ? psw_lo : psw_hi;
 #pragma unroll
     for (int k = 0; k < 2; ++k)
-      if (pact[k]) sl[t + k * NT] = src[po[k]];
+      if (pact[k]) sl[t + k * NT] = ghost ? gv : src[po[k]];
   };
   auto load = [&](int z, T* v) {
     const int zm = z == 0 ? (WALLS ? 0 : nz - 1) : z - 1;

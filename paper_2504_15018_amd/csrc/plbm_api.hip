@@ -1,6 +1,7 @@
 // C ABI of libplbm (declared in include/plbm.h): lattice handles bound to
 // caller-owned device memory, kernel launches on the caller's stream, and the
 // continuous-batching slot table.
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -111,6 +112,12 @@ int make_layout(const plbm_lattice_desc* d, Layout* L, int64_t resident = 0) {
   if (d->pattern != PLBM_PATTERN_AB && d->pattern != PLBM_PATTERN_AA)
     return set_error(PLBM_E_INVALID, "unknown storage pattern");
   const bool aa = d->pattern == PLBM_PATTERN_AA;
+  for (int k = 0; k < 2; ++k) {
+    if (!std::isfinite(d->rho_wall[k]) || d->rho_wall[k] < 0.0)
+      return set_error(PLBM_E_INVALID, "wall densities must be finite and >= 0");
+    if (d->rho_wall[k] > 0.0 && d->bc[d->lattice == PLBM_D2Q9 ? 1 : 2] != PLBM_HALFWAY_BB)
+      return set_error(PLBM_E_INVALID, "a wall density needs walls on the last axis");
+  }
   if (aa && local_shift(d->storage))
     return set_error(PLBM_E_UNSUPPORTED, "the in-place pattern has no locally shifted storage form");
   const bool is2d = d->lattice == PLBM_D2Q9;
@@ -311,6 +318,8 @@ void fill_kparams(plbm_lattice* L) {
   k.ref[0] = local_shift(L->desc.storage) ? L->mem + y.refA : nullptr;
   k.ref[1] = local_shift(L->desc.storage) ? L->mem + y.refB : nullptr;
   k.aa = L->desc.pattern == PLBM_PATTERN_AA;
+  k.rho_wall[0] = L->desc.rho_wall[0];
+  k.rho_wall[1] = L->desc.rho_wall[1];
   k.psi = k.aa ? L->mem + y.psi : nullptr;
   k.aux = reinterpret_cast<double*>(L->mem + y.aux);
   k.uprev = reinterpret_cast<float*>(L->mem + y.uprev);

@@ -230,6 +230,7 @@ struct KParams {
   double rho0_shift;
   int32_t parity;  // batch slots: phase offset of this lattice (its time parity)
   int32_t aa;      // in-place (AA) pattern
+  double rho_wall[2];  // wall densities below / above (wetting walls); <= 0: mirror psi ghost
   int32_t nxb;     // x blocks of one 128-byte line per row (storage layout)
   int64_t zblock;  // bytes of one z plane of stored populations (node data + trash)
   int64_t zdata;   // bytes of the node data of one z plane

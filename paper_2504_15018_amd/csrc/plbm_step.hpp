@@ -315,6 +315,25 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   C shift[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) shift[i] = (C)(L::w[i] * rho0_shift);
+  // psi of the ghost planes beyond the walls: the mirror of the wall-adjacent
+  // plane, or psi(rho_w) of a wall density (wetting walls)
+  const bool wet_lo = WALLS && kp->rho_wall[0] > 0.0, wet_hi = WALLS && kp->rho_wall[1] > 0.0;
+  C psw_lo = 0, psw_hi = 0;
+  if (wet_lo) {
+    bool d_;
+    psw_lo = psi_eval<C>(eos, kp->rho_wall[0], &d_);
+  }
+  if (wet_hi) {
+    bool d_;
+    psw_hi = psi_eval<C>(eos, kp->rho_wall[1], &d_);
+  }
+  auto ghost_psi = [&](int zl, C ps) -> C {
+    if constexpr (WALLS) {
+      if (zl < 0 && wet_lo) return psw_lo;
+      if (zl >= nz && wet_hi) return psw_hi;
+    }
+    return ps;
+  };
 
   // ---- node offsets of this thread, fixed for the whole z march ----
   // oxy[(cx+1) + 3 (cy+1)] = byte offset, within a z plane of stored
@@ -472,13 +491,13 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     const C r = density(fo, as_ref(qo));
     ro = r;
     bool ng;
-    sl[ilds] = psi_eval<C>(eos, (double)r, &ng);
+    sl[ilds] = ghost_psi(zl, psi_eval<C>(eos, (double)r, &ng));
     psi_neg |= ng && ivalid && keep;
     if constexpr (LOC) lds_ref[((zl - z0 + 1) & 3) * PL + ilds] = (C)(RefT)r;
     if constexpr (HALO) {
       bool hng;
       const C rh = density(ho, as_ref(qh));
-      const C ph = psi_eval<C>(eos, (double)rh, &hng);
+      const C ph = ghost_psi(zl, psi_eval<C>(eos, (double)rh, &hng));
       // the spare slots of idle lanes sit past the ring
       (hlds < 4 * PL ? sl : lds_psi)[hlds] = ph;
       if constexpr (LOC) (hlds < 4 * PL ? lds_ref + ((zl - z0 + 1) & 3) * PL : lds_ref)[hlds] = (C)(RefT)rh;
@@ -679,7 +698,7 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
       const int slot = ((zl - z0 + 1) & 3) * PL;
       const C rh = density(ho, as_ref(qh));
       bool hng;
-      const C ph = psi_eval<C>(eos, (double)rh, &hng);
+      const C ph = ghost_psi(zl, psi_eval<C>(eos, (double)rh, &hng));
       (hlds < 4 * PL ? lds_psi + slot : lds_psi)[hlds] = ph;
       if constexpr (LOC) (hlds < 4 * PL ? lds_ref + slot : lds_ref)[hlds] = (C)(RefT)rh;
     };

@@ -17,9 +17,10 @@ Q_OF = {"D2Q9": 9, "D3Q19": 19}
 
 
 def make_desc(lattice, dims, collision="bgk", storage="f64", walls=False, rho0_shift=0.0, mrt_rates=None,
-              pattern="ab"):
+              pattern="ab", rho_wall=(0.0, 0.0)):
     """dims = (nx, ny) for D2Q9 or (nx, ny, nz) for D3Q19; walls on the last axis;
-    pattern "ab" (two population arrays) or "aa" (in place)."""
+    pattern "ab" (two population arrays) or "aa" (in place); rho_wall: wall
+    densities below / above for wetting walls (0: neutral mirror)."""
     d = N.plbm_lattice_desc()
     d.lattice = LATTICE[lattice]
     d.collision = COLLISION[collision]
@@ -31,6 +32,7 @@ def make_desc(lattice, dims, collision="bgk", storage="f64", walls=False, rho0_s
     for a in range(3):
         d.bc[a] = N.PLBM_HALFWAY_BB if (walls and a == last) else N.PLBM_PERIODIC
     d.pattern = PATTERN[pattern]
+    d.rho_wall[0], d.rho_wall[1] = rho_wall
     d.rho0_shift = rho0_shift
     for k, v in enumerate(mrt_rates or (0.0, 0.0, 0.0, 0.0)):
         d.mrt_rates[k] = v
@@ -39,7 +41,7 @@ def make_desc(lattice, dims, collision="bgk", storage="f64", walls=False, rho0_s
 
 class Lattice:
     def __init__(self, lattice, dims, params, collision="bgk", storage="f64", walls=False, rho0_shift=0.0,
-                 mrt_rates=None, stream=None, device="cuda", pattern="ab"):
+                 mrt_rates=None, stream=None, device="cuda", pattern="ab", rho_wall=(0.0, 0.0)):
         import torch
 
         self.name = lattice
@@ -48,7 +50,7 @@ class Lattice:
         self.Q = Q_OF[lattice]
         self.N = int(np.prod(self.dims))
         self.shape = tuple(reversed(self.dims))
-        self.desc = make_desc(lattice, dims, collision, storage, walls, rho0_shift, mrt_rates, pattern)
+        self.desc = make_desc(lattice, dims, collision, storage, walls, rho0_shift, mrt_rates, pattern, rho_wall)
         self.params = params
         self.nbytes = N.plbm_lattice_bytes(self.desc)
         self.mem = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)

@@ -13,7 +13,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libplbm.so")
 
 # ---- constants (plbm.h) ----
-PLBM_ABI_VERSION = 2
+PLBM_ABI_VERSION = 3
 PLBM_OK = 0
 PLBM_E_INVALID = -1
 PLBM_E_UNSUPPORTED = -2
@@ -58,7 +58,8 @@ class plbm_lattice_params(ctypes.Structure):
 
 class plbm_lattice_desc(ctypes.Structure):
     _fields_ = [("lattice", _I32), ("collision", _I32), ("storage", _I32), ("nx", _I32), ("ny", _I32),
-                ("nz", _I32), ("bc", _I32 * 3), ("pattern", _I32), ("rho0_shift", _D), ("mrt_rates", _D * 4)]
+                ("nz", _I32), ("bc", _I32 * 3), ("pattern", _I32), ("rho0_shift", _D), ("mrt_rates", _D * 4),
+                ("rho_wall", _D * 2)]
 
 
 class plbm_shape(ctypes.Structure):

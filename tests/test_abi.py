@@ -173,6 +173,18 @@ def test_inplace_pattern_bytes_and_validation():
     assert ei.value.code == N.PLBM_E_INVALID
 
 
+def test_wall_density_validation():
+    from paper_2504_15018_amd.lattice import make_desc
+    ok = make_desc("D3Q19", (16, 16, 16), walls=True, rho_wall=(6.0, 0.0))
+    assert N.plbm_lattice_bytes(ok) == N.plbm_lattice_bytes(make_desc("D3Q19", (16, 16, 16), walls=True))
+    for bad in (make_desc("D3Q19", (16, 16, 16), rho_wall=(6.0, 0.0)),  # no walls
+                make_desc("D2Q9", (16, 16), walls=True, rho_wall=(-1.0, 0.0)),
+                make_desc("D2Q9", (16, 16), walls=True, rho_wall=(0.0, float("nan")))):
+        with pytest.raises(N.PlbmError) as ei:
+            N.plbm_lattice_bytes(bad)
+        assert ei.value.code == N.PLBM_E_INVALID
+
+
 def test_create_rejects_small_buffer_before_touching_the_device():
     from paper_2504_15018_amd.lattice import make_desc
     d = make_desc("D2Q9", (16, 16))
