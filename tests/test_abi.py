@@ -173,6 +173,21 @@ def test_inplace_pattern_bytes_and_validation():
     assert ei.value.code == N.PLBM_E_INVALID
 
 
+def test_size_limits():
+    """At most 2^31 - 1 nodes (32-bit node indices in the kernels) and 2 GiB of
+    populations per z plane (32-bit byte offsets within a plane)."""
+    from paper_2504_15018_amd.lattice import make_desc
+    assert N.plbm_lattice_bytes(make_desc("D3Q19", (1290, 1290, 1290), storage="f16s", pattern="aa")) > 0
+    with pytest.raises(N.PlbmError) as ei:
+        N.plbm_lattice_bytes(make_desc("D3Q19", (1291, 1291, 1291), storage="f16s"))
+    assert ei.value.code == N.PLBM_E_INVALID
+    # D2Q9 kernel planes are single rows: 2^26 nodes of float64 are 4.8 GB
+    with pytest.raises(N.PlbmError) as ei:
+        N.plbm_lattice_bytes(make_desc("D2Q9", (1 << 26, 4), storage="f64"))
+    assert ei.value.code == N.PLBM_E_UNSUPPORTED
+    assert N.plbm_lattice_bytes(make_desc("D2Q9", (1 << 22, 4), storage="f64")) > 0
+
+
 def test_wall_density_validation():
     from paper_2504_15018_amd.lattice import make_desc
     ok = make_desc("D3Q19", (16, 16, 16), walls=True, rho_wall=(6.0, 0.0))

@@ -1,0 +1,120 @@
+"""Edge cases of the HIP path (through the C ABI).
+
+* Degenerate shapes against the FP64 oracle: extents of 1 and 2 (a node is its
+  own periodic neighbour), a single plane between two walls, lattices smaller
+  than one tile, in both storage patterns; float64 bar 1e-12, float32 2e-6 per
+  step (as the other parity tests).
+* Zero steps change nothing.
+* The largest lattice the ABI accepts: 1290^3 = 2 146 689 000 nodes (2^31 - 1 is
+  the limit of the 32-bit node indices), in-place half-precision storage
+  (about 190 GB of HBM).  The oracle cannot run at that size; the checks hold
+  at any size: no health flag, mass conserved to the storage's rounding (1e-4), total
+  momentum zero by symmetry, and the droplet's density field mirror-symmetric
+  about its centre on sampled lines.
+"""
+import numpy as np
+import pytest
+
+from oracle import step as S
+
+from gpu_cases import abs_max, fmt, lib_params, oracle_params, rel_max, random_state, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [
+    # lattice, dims, collision, storage, walls, pattern, steps
+    ("D3Q19", (1, 1, 1), "bgk", "f64", False, "ab", 3),
+    ("D3Q19", (1, 1, 5), "mrt", "f64", True, "aa", 4),
+    ("D3Q19", (2, 3, 1), "mrt", "f64", False, "ab", 3),
+    ("D3Q19", (3, 1, 4), "mrt", "f64", True, "ab", 5),
+    ("D3Q19", (5, 4, 1), "bgk", "f64", True, "aa", 3),  # one plane between two walls
+    ("D3Q19", (65, 9, 2), "mrt", "f32", True, "aa", 3),
+    ("D3Q19", (7, 2, 2), "bgk", "f32", False, "ab", 4),
+    ("D2Q9", (1, 9), "mrt", "f64", False, "ab", 4),
+    ("D2Q9", (7, 1), "bgk", "f64", True, "aa", 3),  # one row between two walls
+    ("D2Q9", (1, 1), "bgk", "f64", False, "aa", 2),
+    ("D2Q9", (129, 2), "mrt", "f64", True, "ab", 5),
+]
+
+
+@pytest.mark.parametrize("case", SHAPES, ids=lambda c: f"{c[0]}-{'x'.join(map(str, c[1]))}-{c[2]}-{c[3]}-"
+                                                         f"{'bb' if c[4] else 'per'}-{c[5]}")
+def test_degenerate_shapes_match_the_oracle(case):
+    require_gpu()
+    from paper_2504_15018_amd.lattice import Lattice
+    lattice, dims, collision, storage, walls, pattern, steps = case
+    fmt("edge_shape", case=case)
+    f0 = random_state(lattice, dims, 23)
+    op = oracle_params(lattice, collision=collision, walls=walls)
+    lat = Lattice(lattice, dims, lib_params(), collision=collision, storage=storage, walls=walls, pattern=pattern)
+    lat.write_populations(f0)
+    if storage == "f32":
+        f0 = f0.astype(np.float32).astype(np.float64)
+    assert np.array_equal(lat.populations(), f0)
+    lat.step(steps)
+    f_ref = S.run(op, f0, steps)
+    tf, tu = (1e-12, 1e-12) if storage == "f64" else (2e-6 * steps, 1e-6 * steps)
+    assert rel_max(lat.populations(), f_ref) <= tf
+    rho, u = lat.moments()
+    rho_ref, u_ref = S.moments(op, f_ref)
+    assert rel_max(rho, rho_ref) <= tf
+    assert abs_max(u, u_ref) <= tu
+    d = lat.reduce()
+    # the +-30 % random states reach 1.3 rho_l, where the psi radicand can turn negative (clamped on both sides,
+    # PSI_NEG raised): only NaN and rho <= 0 are failures here
+    assert not (d.flags & 3) and d.time == steps
+    lat.close()
+
+
+@pytest.mark.parametrize("pattern", ["ab", "aa"])
+def test_zero_steps_change_nothing(pattern):
+    require_gpu()
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("edge_zero_steps", pattern=pattern)
+    dims = (33, 17, 9)
+    f0 = random_state("D3Q19", dims, 2)
+    lat = Lattice("D3Q19", dims, lib_params(), collision="mrt", storage="f64", pattern=pattern)
+    lat.write_populations(f0)
+    lat.step(0)
+    assert lat.time == 0 and np.array_equal(lat.populations(), f0)
+    lat.step(3)
+    f3 = lat.populations()
+    lat.step(0)
+    assert lat.time == 3 and np.array_equal(lat.populations(), f3)
+    lat.close()
+
+
+def test_largest_lattice_1290_cubed():
+    require_gpu()
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+    n = 1290
+    fmt("edge_max_size", nodes=n ** 3)
+    prm = lib_params()
+    lat = Lattice("D3Q19", (n, n, n), prm, collision="mrt", storage="f16s", pattern="aa")
+    fmt("edge_max_size_bytes", gb=f"{lat.nbytes / 1e9:.1f}")
+    c = n / 2.0 - 0.5  # the centre between two nodes: the lattice is mirror-symmetric about it
+    lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=5.0, R=300.0, centre=[c, c, c])
+    d0 = lat.reduce()
+    lat.step(5)
+    d = lat.reduce()
+    fmt("edge_max_size_result", mass0=f"{d0.mass:.9e}", mass=f"{d.mass:.9e}", max_u=f"{d.max_u:.3e}",
+        mom=[f"{m:.2e}" for m in d.momentum])
+    assert d.flags == 0 and d.time == 5
+    # half-precision storage of deviations from w_i rho_l: a uniform vapour rounds coherently (every vapour
+    # node carries the same rounding error each step), so mass moves by up to ~1e-3 per step in the worst
+    # case; measured 4.6e-6 after 5 steps
+    assert abs(d.mass - d0.mass) <= 1e-4 * d0.mass
+    assert max(abs(m) for m in d.momentum) <= 1e-6 * d.mass
+    # density on three lines through the centre: nodes near index 0 against their mirror images near
+    # index 2^31 (68 GB of float64 moments come back to the host)
+    fmt("edge_max_size_moments")
+    rho, _ = lat.moments()
+    m = n // 2
+    for line in (rho[m, m, :], rho[m, :, m], rho[:, m, m]):
+        v = np.array(line)
+        # exact up to half-precision rounding of mirrored values (about 1e-4 of the liquid density)
+        assert np.max(np.abs(v - v[::-1])) <= 1e-3 * np.max(v)
+        assert v[m] > 0.9 * prm.rho_l and v[0] < 1.5 * prm.rho_v
+    del rho
+    lat.close()
