@@ -35,16 +35,12 @@ SOURCES = {
     # SIMD, one workgroup per CU), float32 with loads a full plane iteration
     # ahead; float64 64 x 4 tiles (seven waves within 256 registers).
     # Populations are stored with the non-temporal hint except by bfloat16 and
-    # the locally shifted formats (slower with it).  The psi pass of the
-    # in-place pattern splits each tile's z chunk over 8 workgroups for 16-bit
-    # storage and keeps one for float32 / float64 (measured).
-    "plbm_k_f64.hip": ["-ffp-contract=off", "-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=4",
-                       "-DPLBM_PSI_SPLIT=1"],
-    "plbm_k_f32.hip": ["-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3", "-DPLBM_PSI_SPLIT=1"],
-    "plbm_k_f16s.hip": ["-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3",
-                        "-DPLBM_PSI_SPLIT=8"],
+    # the locally shifted formats (slower with it).
+    "plbm_k_f64.hip": ["-ffp-contract=off", "-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=4"],
+    "plbm_k_f32.hip": ["-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3"],
+    "plbm_k_f16s.hip": ["-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3"],
     "plbm_k_bf16s.hip": ["-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3",
-                         "-DPLBM_NT_STORE=0", "-DPLBM_PSI_SPLIT=8"],
+                         "-DPLBM_NT_STORE=0"],
     "plbm_k_f16r.hip": ["-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3",
                         "-DPLBM_NT_STORE=0"],
     "plbm_k_bf16r.hip": ["-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3",

@@ -114,29 +114,24 @@ __device__ __forceinline__ typename St::C aa_dec(typename St::T v, typename St::
 #endif
 
 // psi(rho(x, t)) of every node of a tile's z chunk into kp->psi.  The chunk
-// may be split over PSI_SPLIT workgroups (the update's tiling gives about one
-// workgroup per CU; 16-bit storage streams faster with more).
-#ifndef PLBM_PSI_SPLIT
-#define PLBM_PSI_SPLIT 4
-#endif
-constexpr int PSI_SPLIT = PLBM_PSI_SPLIT;
-
+// is split over `split` workgroups (the update's tiling gives about one
+// workgroup per CU, too few for a pass that only streams populations in).
 template <class L, class St, int TX, int TY, bool WALLS>
 __global__ __launch_bounds__(TX* TY) void k_aa_psi(const KParams* __restrict__ P, const WorkItem* __restrict__ work,
-                                                   int32_t nwork, int32_t phase) {
+                                                   int32_t nwork, int32_t phase, int32_t split) {
   using T = typename St::T;
   using C = typename St::C;
   constexpr int Q = L::Q;
   // consecutive (tile, sub-chunk) items share an XCD, as in the update
   const int item = xcd_remap(blockIdx.x, gridDim.x);
   AaTile tl;
-  if (!aa_tile(item / PSI_SPLIT, P, work, nwork, TX, TY, &tl)) return;
+  if (!aa_tile(item / split, P, work, nwork, TX, TY, &tl)) return;
   const KParams* __restrict__ kp = tl.kp;
   const int nx = kp->nx, ny = kp->ny, nz = kp->nz;
   {
-    const int sub = item % PSI_SPLIT, len = tl.z1 - tl.z0;
-    tl.z1 = tl.z0 + len * (sub + 1) / PSI_SPLIT;
-    tl.z0 = tl.z0 + len * sub / PSI_SPLIT;
+    const int sub = item % split, len = tl.z1 - tl.z0;
+    tl.z1 = tl.z0 + len * (sub + 1) / split;
+    tl.z0 = tl.z0 + len * sub / split;
   }
   const int t = threadIdx.x;
   const int gx = tl.x0 + t % TX, gy = tl.y0 + t / TX;

@@ -269,6 +269,17 @@ int aux_blocks(int64_t N) {
   return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
 }
 
+// Workgroups per tile chunk of the in-place pattern's psi pass (measured on
+// 256^3: float32 and float64 fastest with one, 16-bit storage with eight;
+// PLBM_PSI_SPLIT overrides, for tuning).
+int psi_split(int storage) {
+  if (const char* e = std::getenv("PLBM_PSI_SPLIT")) {
+    int v = std::atoi(e);
+    if (v > 0) return v;
+  }
+  return storage_bytes(storage) == 2 ? 8 : 1;
+}
+
 int run_step_kernel(plbm_lattice* L, int mode, int phase, double* orho, double* ou) {
   StepLaunch a{};
   a.lattice = L->desc.lattice;
@@ -276,6 +287,7 @@ int run_step_kernel(plbm_lattice* L, int mode, int phase, double* orho, double* 
   a.mode = mode;
   a.walls = L->kp.bb_z;
   a.aa = L->kp.aa;
+  a.psplit = psi_split(L->desc.storage);
   a.nblocks = L->lay.ntiles;
   a.stream = L->stream;
   a.P = L->kp_dev;
@@ -722,6 +734,7 @@ int batch_launch(plbm_batch* b, int mode, int phase) {
     a.mode = mode;
     a.walls = gr.walls;
     a.aa = gr.aa;
+    a.psplit = psi_split(gr.storage);
     a.nblocks = gr.count;
     a.stream = b->stream;
     a.P = b->slots_dev;

@@ -21,8 +21,8 @@ static hipError_t go_aa(const StepLaunch& a) {
   if constexpr (PLBM_ST::local) {
     return hipErrorInvalidValue;
   } else {
-    hipLaunchKernelGGL((k_aa_psi<L, PLBM_ST, TS::TX, TS::TY, WALLS>), dim3(a.nblocks * PSI_SPLIT), dim3(TS::TX * TS::TY), 0,
-                       a.stream, a.P, a.work, a.nwork, a.phase);
+    hipLaunchKernelGGL((k_aa_psi<L, PLBM_ST, TS::TX, TS::TY, WALLS>), dim3((uint32_t)a.nblocks * (uint32_t)a.psplit),
+                       dim3(TS::TX * TS::TY), 0, a.stream, a.P, a.work, a.nwork, a.phase, a.psplit);
     hipLaunchKernelGGL((k_aa_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, WALLS>), dim3(a.nblocks),
                        dim3(TS::TX * TS::TY), 0, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
     return hipGetLastError();

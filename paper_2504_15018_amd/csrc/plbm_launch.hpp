@@ -47,6 +47,7 @@ struct StepLaunch {
   int mode;     // 0 step, 1 moments, 2 reduce
   int walls;    // half-way bounce-back on the marching axis
   int aa;       // in-place pattern: psi pass, then the in-place update
+  int psplit;   // in-place pattern: workgroups per tile chunk of the psi pass (>= 1)
   int nblocks;
   hipStream_t stream;
   const KParams* P;
