@@ -172,13 +172,8 @@ struct StBF16S {
   static __device__ __forceinline__ C dec(T v, C shift) {
     return __uint_as_float(((uint32_t)v) << 16) + shift;
   }
-  static __device__ __forceinline__ T enc(C f, C shift) {
-    float d = f - shift;
-    uint32_t u = __float_as_uint(d);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-    return (uint16_t)(u >> 16);
-  }
+  // round to nearest even in hardware (v_cvt_pk_bf16_f32); NaN stays a quiet NaN
+  static __device__ __forceinline__ T enc(C f, C shift) { return __builtin_bit_cast(uint16_t, (__bf16)(f - shift)); }
   static __device__ __forceinline__ double dec64(T v, double shift) {
 #pragma clang fp contract(off)
     return (double)__uint_as_float(((uint32_t)v) << 16) + shift;

@@ -29,6 +29,9 @@ namespace plbm {
 #ifndef PLBM_MIN_WAVES
 #define PLBM_MIN_WAVES 2  // waves per SIMD the register allocation must allow
 #endif
+#ifndef PLBM_HALO_PRIO
+#define PLBM_HALO_PRIO 1  // wave issue priority of the halo waves (0: that of the tile waves)
+#endif
 
 enum : int { COLL_BGK = 0, COLL_MRT = 1 };
 enum : int { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_REDUCE = 2 };
@@ -731,6 +734,9 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
 #endif
   };
   if constexpr (SPLIT) {
+    // Every tile wave waits at the plane barrier for the psi ring the halo
+    // waves produce; issue priority for the halo waves shortens that wait.
+    if (PLBM_HALO_PRIO > 0 && halo_thread) __builtin_amdgcn_s_setprio(PLBM_HALO_PRIO);
     if (halo_thread)
       march_halo();
     else
