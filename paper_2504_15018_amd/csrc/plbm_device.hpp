@@ -146,13 +146,24 @@ struct StF32 {
   static __device__ __forceinline__ T enc64(double f, double) { return (float)f; }
 };
 
+// The shift is added and subtracted without contraction: with a per-node
+// reference the shift is a product w_i rho_ref, and a multiply fused into the
+// encoder's subtraction but not into the decoder's addition (or the reverse)
+// leaves a systematic difference of one rounding of that product per
+// population and step, which a uniform region accumulates as mass drift.
 struct StF16S {
   using T = _Float16;
   using C = float;
   static constexpr bool shifted = true;
   static constexpr bool local = false;
-  static __device__ __forceinline__ C dec(T v, C shift) { return (float)v + shift; }
-  static __device__ __forceinline__ T enc(C f, C shift) { return (_Float16)(f - shift); }  // RNE
+  static __device__ __forceinline__ C dec(T v, C shift) {
+#pragma clang fp contract(off)
+    return (float)v + shift;
+  }
+  static __device__ __forceinline__ T enc(C f, C shift) {  // RNE
+#pragma clang fp contract(off)
+    return (_Float16)(f - shift);
+  }
   // float64 forms: plain operation order, no fused multiply-add with the shift
   static __device__ __forceinline__ double dec64(T v, double shift) {
 #pragma clang fp contract(off)
@@ -170,10 +181,14 @@ struct StBF16S {
   static constexpr bool shifted = true;
   static constexpr bool local = false;
   static __device__ __forceinline__ C dec(T v, C shift) {
+#pragma clang fp contract(off)
     return __uint_as_float(((uint32_t)v) << 16) + shift;
   }
   // round to nearest even in hardware (v_cvt_pk_bf16_f32); NaN stays a quiet NaN
-  static __device__ __forceinline__ T enc(C f, C shift) { return __builtin_bit_cast(uint16_t, (__bf16)(f - shift)); }
+  static __device__ __forceinline__ T enc(C f, C shift) {
+#pragma clang fp contract(off)
+    return __builtin_bit_cast(uint16_t, (__bf16)(f - shift));
+  }
   static __device__ __forceinline__ double dec64(T v, double shift) {
 #pragma clang fp contract(off)
     return (double)__uint_as_float(((uint32_t)v) << 16) + shift;
