@@ -17,8 +17,9 @@ namespace plbm {
 struct WorkItem;
 struct ShapeK;
 
-// Compile-time tile shapes: D3Q19 32 x 8 nodes per workgroup of 256 threads
-// (one node per thread per plane); D2Q9 rows of 128 nodes per 128 threads.
+// Compile-time tile shapes (one node per thread per plane): D3Q19 TX x TY
+// nodes, set per storage translation unit (default 32 x 8); D2Q9 rows of 256
+// nodes.
 template <class L>
 struct TileShape;
 #ifndef PLBM_D3_TX
@@ -28,16 +29,19 @@ struct TileShape;
 #define PLBM_D3_TY 8
 #endif
 // With PLBM_HALO_SPLIT the workgroup adds whole waves for the halo ring
-// (D3Q19: (TX+2)(TY+2) - TX TY nodes; D2Q9: the two row ends).
+// (D3Q19: (TX+2)(TY+2) - TX TY nodes; D2Q9: the two row ends of 256-node rows).
 template <>
 struct TileShape<D3Q19L> {
   static constexpr int TX = PLBM_D3_TX, TY = PLBM_D3_TY;
   static constexpr int H = (TX + 2) * (TY + 2) - TX * TY;
   static constexpr int NT = TX * TY + (PLBM_HALO_SPLIT ? 64 * ((H + 63) / 64) : 0);
 };
+#ifndef PLBM_D2_TX
+#define PLBM_D2_TX 256
+#endif
 template <>
 struct TileShape<D2Q9L> {
-  static constexpr int TX = 128, TY = 1;
+  static constexpr int TX = PLBM_D2_TX, TY = 1;
   static constexpr int NT = TX * TY + (PLBM_HALO_SPLIT ? 64 : 0);
 };
 
