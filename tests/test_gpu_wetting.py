@@ -141,3 +141,31 @@ def test_contact_angle_follows_the_wall_density():
     assert 85.0 <= mirror <= 95.0  # neutral wetting
     assert all(a > b + 8.0 for a, b in zip(angles, angles[1:])), angles  # monotone in rho_w
     assert angles[0] >= 140.0 and angles[-1] <= 50.0  # hydrophobic to hydrophilic
+
+
+def test_contact_angle_3d_follows_the_wall_density():
+    """D3Q19 sessile droplet (float64, MRT): the angle in the mid x-z plane orders like the 2-D one."""
+    require_gpu()
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("contact_angle_3d")
+    rv, rl, _ = pr_coex(TR)
+    n, nz = 112, 56
+    prm = lib_params(tr=TR)
+    angles = {}
+    for frac in (0.2, None, 0.5):
+        rw = 0.0 if frac is None else rv + frac * (rl - rv)
+        lat = Lattice("D3Q19", (n, n, nz), prm, collision="mrt", storage="f64", walls=True, rho_wall=(rw, 0.0))
+        lat.init_shape(N.PLBM_SHAPE_DROPLET, rl, rv, W=5.0, R=24.0, centre=[n / 2.0, n / 2.0, 0.0])
+        m0 = lat.reduce().mass
+        lat.step(16000)
+        d = lat.reduce()
+        rho, _ = lat.moments()
+        lat.close()
+        assert d.flags == 0 and abs(d.mass - m0) <= 1e-10 * m0
+        theta, R = _contact_angle(rho[:, n // 2, :], 0.5 * (rv + rl), y_min=3)  # (z, x) plane through the centre
+        angles[frac] = theta
+        fmt("contact_angle_3d_result", frac=frac, rho_w=f"{rw:.4f}", theta=f"{theta:.1f}", R=f"{R:.1f}",
+            max_u=f"{d.max_u:.2e}")
+    assert angles[0.2] > angles[None] + 8.0 > angles[0.5] + 16.0
+    assert 80.0 <= angles[None] <= 100.0
