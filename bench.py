@@ -49,7 +49,9 @@ def kernel_source_hash():
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2504_15018_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    h.update(" ".join(build.COMMON[1:] + build.SOURCES["plbm_k_f32.hip"]).encode())
+    # compile flags without the include directories (absolute paths differ between checkouts)
+    flags = [a for a in build.COMMON[1:] + build.SOURCES["plbm_k_f32.hip"] if not a.startswith("-I")]
+    h.update(" ".join(flags).encode())
     return h.hexdigest()[:16]
 
 
