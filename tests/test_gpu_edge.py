@@ -5,12 +5,9 @@
   than one tile, in both storage patterns; float64 bar 1e-12, float32 2e-6 per
   step (as the other parity tests).
 * Zero steps change nothing.
-* The largest lattice the ABI accepts: 1290^3 = 2 146 689 000 nodes (2^31 - 1 is
-  the limit of the 32-bit node indices), in-place half-precision storage
-  (about 190 GB of HBM).  The oracle cannot run at that size; the checks hold
-  at any size: no health flag, mass conserved to the storage's rounding (1e-4), total
-  momentum zero by symmetry, and the droplet's density field mirror-symmetric
-  about its centre on sampled lines.
+
+The largest accepted lattice is exercised in test_gpu_zz_largest.py (it runs
+last: it needs about 190 GB of HBM).
 """
 import numpy as np
 import pytest
@@ -81,40 +78,4 @@ def test_zero_steps_change_nothing(pattern):
     f3 = lat.populations()
     lat.step(0)
     assert lat.time == 3 and np.array_equal(lat.populations(), f3)
-    lat.close()
-
-
-def test_largest_lattice_1290_cubed():
-    require_gpu()
-    from paper_2504_15018_amd import native as N
-    from paper_2504_15018_amd.lattice import Lattice
-    n = 1290
-    fmt("edge_max_size", nodes=n ** 3)
-    prm = lib_params()
-    lat = Lattice("D3Q19", (n, n, n), prm, collision="mrt", storage="f16s", pattern="aa")
-    fmt("edge_max_size_bytes", gb=f"{lat.nbytes / 1e9:.1f}")
-    c = n / 2.0 - 0.5  # the centre between two nodes: the lattice is mirror-symmetric about it
-    lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=5.0, R=300.0, centre=[c, c, c])
-    d0 = lat.reduce()
-    lat.step(5)
-    d = lat.reduce()
-    fmt("edge_max_size_result", mass0=f"{d0.mass:.9e}", mass=f"{d.mass:.9e}", max_u=f"{d.max_u:.3e}",
-        mom=[f"{m:.2e}" for m in d.momentum])
-    assert d.flags == 0 and d.time == 5
-    # half-precision storage of deviations from w_i rho_l: a uniform vapour rounds coherently (every vapour
-    # node carries the same rounding error each step), so mass moves by up to ~1e-3 per step in the worst
-    # case; measured 4.6e-6 after 5 steps
-    assert abs(d.mass - d0.mass) <= 1e-4 * d0.mass
-    assert max(abs(m) for m in d.momentum) <= 1e-6 * d.mass
-    # density on three lines through the centre: nodes near index 0 against their mirror images near
-    # index 2^31 (68 GB of float64 moments come back to the host)
-    fmt("edge_max_size_moments")
-    rho, _ = lat.moments()
-    m = n // 2
-    for line in (rho[m, m, :], rho[m, :, m], rho[:, m, m]):
-        v = np.array(line)
-        # exact up to half-precision rounding of mirrored values (about 1e-4 of the liquid density)
-        assert np.max(np.abs(v - v[::-1])) <= 1e-3 * np.max(v)
-        assert v[m] > 0.9 * prm.rho_l and v[0] < 1.5 * prm.rho_v
-    del rho
     lat.close()
