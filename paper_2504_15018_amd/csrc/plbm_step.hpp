@@ -572,7 +572,9 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
           if (WALLS && cz != 0) rd = (cz > 0 ? zhi : zlo) ? r_0[ilds] : rd;
           gst<T>(dz + i * QB, soff, St::enc(fs[i], (C)L::w[i] * rd));
         }
-        const uint32_t ridx = ivalid ? nid : (uint32_t)N + (uint32_t)t;
+        // ragged-tile lanes write one of the 256 spare slots after the N
+        // nodes (never read; a tile has up to 1024 threads)
+        const uint32_t ridx = ivalid ? nid : (uint32_t)N + ((uint32_t)t & 255u);
         ref_dst[ridx] = (RefT)rho;
       } else {
 #pragma unroll
