@@ -8,8 +8,10 @@ temperature of the lattice Peng-Robinson EOS, droplet radius.  The loop
     one stay within the HBM budget; a request that does not fit waits;
   * gives each admitted request its own lattice (a PyTorch device buffer),
     initialised on the device (plbm_init_shape) and attached to the batch;
-  * advances every resident lattice together with plbm_batch_step (one launch
-    per lattice type per step, replayed from a captured HIP graph);
+  * advances the resident lattices of each lattice kind together with
+    plbm_batch_step (one batch and stream per kind, one launch per lattice
+    type per step, replayed from a captured HIP graph); the kinds advance at
+    their own rates;
   * every `check_every` steps reads the per-lattice diagnostics
     (plbm_batch_diag): a lattice whose residual max|u(t) - u(t-k)|/k is at or
     below `tol` is converged; NaN or rho <= 0 marks it failed; a lattice that
@@ -76,7 +78,35 @@ def from_synth(reqs):
     return [Request(r["id"], r["arrival"], r["lattice"], r["dims"], r["T_over_Tc"], r["radius"]) for r in reqs]
 
 
+class Lane:
+    """One batch of resident lattices of one lattice kind, on its own stream."""
+
+    def __init__(self, torch, kind, max_slots, max_tiles):
+        self.kind = kind
+        self.stream = torch.cuda.Stream()  # default priority
+        nb = N.plbm_batch_bytes(max_slots, max_tiles)
+        self._bmem = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+        ptr = (self._bmem.data_ptr() + 255) // 256 * 256
+        self.batch = N.plbm_batch_create(max_slots, max_tiles, ptr, nb, self.stream.cuda_stream)
+        self.resident = {}  # slot -> Request
+        self.queue = []     # admitted in arrival order
+        self.inflight = 0   # steps enqueued and not yet checked
+        self.event = None
+
+
 class Server:
+    """Serving loop over one lane per lattice kind (D2Q9, D3Q19).
+
+    Each lane is a batch on its own stream and advances at its own rate: a
+    D2Q9 step of a few small lattices takes tens of microseconds, a D3Q19 step
+    of large ones milliseconds, and lattices of one kind need similar step
+    counts, so the cheap kind is not held to the other's pace.  The loop
+    enqueues `check_every` steps on every idle lane without waiting, then
+    polls the lanes' completion events; a finished chunk is checked (residual,
+    health) and the lane's queue is admitted while that lane is idle.  The HBM
+    budget is shared; each lane keeps arrival order in its own queue.
+    """
+
     def __init__(self, budget_bytes, max_slots=64, max_tiles=1 << 20, check_every=100, tol=1e-8,
                  max_steps=2_000_000, storage="f32", collision="bgk", keep_lattices=False, width=5.0,
                  pattern="ab"):
@@ -84,7 +114,8 @@ class Server:
 
         self.torch = torch
         self.budget = int(budget_bytes)
-        self.max_slots = max_slots
+        self.max_slots = max_slots  # per lane
+        self.max_tiles = max_tiles
         self.check_every = int(check_every)
         self.tol = tol
         self.max_steps = int(max_steps)
@@ -93,23 +124,29 @@ class Server:
         self.pattern = pattern  # "aa": in place, about half the population memory per resident lattice
         self.keep = keep_lattices
         self.width = width
-        self.stream = torch.cuda.Stream()
-        nb = N.plbm_batch_bytes(max_slots, max_tiles)
-        self._bmem = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
-        ptr = (self._bmem.data_ptr() + 255) // 256 * 256
-        self.batch = N.plbm_batch_create(max_slots, max_tiles, ptr, nb, self.stream.cuda_stream)
-        self.resident = {}  # slot -> Request
+        self.lanes = {}
         self.used = 0
         self.peak_used = 0
         self.peak_resident = 0
 
+    def _lane(self, kind):
+        if kind not in self.lanes:
+            self.lanes[kind] = Lane(self.torch, kind, self.max_slots, self.max_tiles)
+        return self.lanes[kind]
+
+    @property
+    def resident(self):
+        return {(k, s): r for k, lane in self.lanes.items() for s, r in lane.resident.items()}
+
     def close(self):
-        """Cancel what is still resident (its `done` stays None) and release the batch."""
-        self.stream.synchronize()
-        for r in list(self.resident.values()):
-            self._retire(r, "cancelled", None)
-        N.plbm_batch_destroy(self.batch)
-        self.batch = None
+        """Cancel what is still resident (its `done` stays None) and release the batches."""
+        for lane in self.lanes.values():
+            lane.stream.synchronize()
+            for r in list(lane.resident.values()):
+                self._retire(lane, r, "cancelled", None)
+            N.plbm_batch_destroy(lane.batch)
+            lane.batch = None
+        self.lanes = {}
 
     # ---- admission ----
     def _desc_bytes(self, req):
@@ -117,32 +154,64 @@ class Server:
         return N.plbm_lattice_bytes(make_desc(req.lattice, req.dims, self.collision, self.storage,
                                               pattern=self.pattern)) + 256
 
-    def _admit(self, req, now):
+    def _admit(self, lane, req, now):
         req.params = N.plbm_params_pr_lattice(req.T_over_Tc, 0.326, 2.0, 1.0, 1.0, 1.0)
         lat = Lattice(req.lattice, req.dims, req.params, collision=self.collision, storage=self.storage,
-                      stream=self.stream, pattern=self.pattern)
+                      stream=lane.stream, pattern=self.pattern)
         req.lat = lat
         centre = [n / 2.0 for n in req.dims]
         lat.init_shape(N.PLBM_SHAPE_DROPLET, req.params.rho_l, req.params.rho_v, W=self.width, R=req.radius,
                        centre=centre)
         lat.reduce()  # stores u(0) for the first residual
-        req.slot = N.plbm_batch_attach(self.batch, lat.h)
+        req.slot = N.plbm_batch_attach(lane.batch, lat.h)
         req.admit = now
         req.status = "running"
-        self.resident[req.slot] = req
+        lane.resident[req.slot] = req
         self.used += req.bytes
         self.peak_used = max(self.peak_used, self.used)
-        self.peak_resident = max(self.peak_resident, len(self.resident))
+        self.peak_resident = max(self.peak_resident, sum(len(ln.resident) for ln in self.lanes.values()))
 
-    def _retire(self, req, status, now):
-        N.plbm_batch_detach(self.batch, req.slot)
-        del self.resident[req.slot]
+    def _retire(self, lane, req, status, now):
+        N.plbm_batch_detach(lane.batch, req.slot)
+        del lane.resident[req.slot]
         req.status = status
         req.done = now
         self.used -= req.bytes
         if not self.keep:
             req.lat.close()
             req.lat = None
+
+    def _admit_queue(self, lane, now):
+        for _ in range(admissible(lane.queue, len(lane.resident), self.used, self.budget, self.max_slots)):
+            req = lane.queue.pop(0)
+            try:
+                self._admit(lane, req, now)
+            except N.PlbmError as e:  # e.g. no coexistence at this T/Tc: refuse the request, keep serving
+                if req.lat is not None:
+                    req.lat.close()
+                    req.lat = None
+                req.status = "rejected"
+                req.error = str(e)
+
+    def _check(self, lane, now):
+        """Residual and health of every lattice of a lane whose chunk has completed."""
+        n = lane.inflight
+        diag = N.plbm_batch_diag(lane.batch, self.max_slots)
+        served = 0
+        for slot, req in list(lane.resident.items()):
+            d = diag[slot]
+            req.steps += n
+            served += req.nodes * n
+            req.residual = d.max_du_per_step
+            if d.flags & (N.PLBM_FLAG_NAN | N.PLBM_FLAG_RHO_NONPOS):
+                self._retire(lane, req, "failed", now)
+            elif req.residual <= self.tol:
+                self._retire(lane, req, "converged", now)
+            elif req.steps >= self.max_steps:
+                self._retire(lane, req, "capped", now)
+        lane.inflight = 0
+        lane.event = None
+        return served
 
     # ---- the loop ----
     def run(self, requests, time_limit=None, log=None):
@@ -152,50 +221,46 @@ class Server:
             if r.bytes > self.budget:
                 r.status = "rejected"
         pending = [r for r in reqs if r.status != "rejected"]
-        queue = []
         t0 = time.perf_counter()
         served_updates = 0
         i = 0
-        while i < len(pending) or queue or self.resident:
+
+        def busy():
+            return any(lane.resident or lane.queue or lane.inflight for lane in self.lanes.values())
+
+        while i < len(pending) or busy():
             now = time.perf_counter() - t0
             if time_limit is not None and now > time_limit:
                 break
             while i < len(pending) and pending[i].arrival <= now:
-                queue.append(pending[i])
+                self._lane(pending[i].lattice).queue.append(pending[i])
                 i += 1
-            for _ in range(admissible(queue, len(self.resident), self.used, self.budget, self.max_slots)):
-                req = queue.pop(0)
-                try:
-                    self._admit(req, time.perf_counter() - t0)
-                except N.PlbmError as e:  # e.g. no coexistence at this T/Tc: refuse the request, keep serving
-                    if req.lat is not None:
-                        req.lat.close()
-                        req.lat = None
-                    req.status = "rejected"
-                    req.error = str(e)
-            if not self.resident:
-                if i < len(pending):
+            progressed = False
+            for lane in self.lanes.values():
+                if lane.inflight and lane.event.query():
+                    served_updates += self._check(lane, time.perf_counter() - t0)
+                    progressed = True
+                if not lane.inflight:
+                    if lane.queue:
+                        self._admit_queue(lane, time.perf_counter() - t0)
+                    if lane.resident:
+                        N.plbm_batch_step(lane.batch, self.check_every)
+                        lane.inflight = self.check_every
+                        lane.event = self.torch.cuda.Event()
+                        lane.event.record(lane.stream)
+                        progressed = True
+            if not progressed:
+                # nothing completed: wait a little for the next chunk or arrival
+                if not any(lane.inflight for lane in self.lanes.values()) and i < len(pending):
                     time.sleep(max(0.0, min(pending[i].arrival - now, 0.01)))
-                continue
-            n = self.check_every
-            N.plbm_batch_step(self.batch, n)
-            diag = N.plbm_batch_diag(self.batch, self.max_slots)
-            now = time.perf_counter() - t0
-            for slot, req in list(self.resident.items()):
-                d = diag[slot]
-                req.steps += n
-                served_updates += req.nodes * n
-                req.residual = d.max_du_per_step
-                if d.flags & (N.PLBM_FLAG_NAN | N.PLBM_FLAG_RHO_NONPOS):
-                    self._retire(req, "failed", now)
-                elif req.residual <= self.tol:
-                    self._retire(req, "converged", now)
-                elif req.steps >= self.max_steps:
-                    self._retire(req, "capped", now)
+                else:
+                    time.sleep(2e-5)
             if log is not None:
-                log(f"[serve] t={now:.2f}s resident={len(self.resident)} queued={len(queue)} "
+                log(f"[serve] t={now:.2f}s resident={len(self.resident)} "
+                    f"queued={sum(len(ln.queue) for ln in self.lanes.values())} "
                     f"done={sum(r.done is not None for r in reqs)}/{len(reqs)}")
-        self.stream.synchronize()
+        for lane in self.lanes.values():
+            lane.stream.synchronize()
         makespan = time.perf_counter() - t0
         out = summarize(reqs, makespan, served_updates)
         out.update(peak_bytes=self.peak_used, peak_resident=self.peak_resident, budget_bytes=self.budget)

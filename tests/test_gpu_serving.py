@@ -1,6 +1,7 @@
 """The serving loop on the GPU: requests arriving while others run are admitted
-as memory frees up, never beyond the HBM budget, in arrival order, and each
-served result is bitwise the same as the same solve run alone."""
+as memory frees up, never beyond the HBM budget, in arrival order within each
+lattice kind (each kind has its own batch and stream), and each served result
+is bitwise the same as the same solve run alone."""
 import numpy as np
 import pytest
 
@@ -30,9 +31,10 @@ def test_serving_small_stream_matches_solo_runs(pattern):
     print({k: v for k, v in out.items() if k != "records"}, flush=True)
     assert out["unfinished"] == 0 and out["rejected"] == 0 and out["failed"] == 0
     assert out["peak_bytes"] <= srv.budget
-    order = sorted(reqs, key=lambda r: r.arrival)
-    admits = [r.admit for r in order]
-    assert admits == sorted(admits)  # FIFO
+    for kind in ("D2Q9", "D3Q19"):  # FIFO within each lattice kind's lane
+        order = sorted((r for r in reqs if r.lattice == kind), key=lambda r: r.arrival)
+        admits = [r.admit for r in order]
+        assert admits == sorted(admits)
     assert any(r.admit > r.arrival + 1e-3 for r in reqs)  # some requests waited for memory
     for r in reqs:
         assert r.status in ("converged", "capped")
