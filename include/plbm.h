@@ -87,8 +87,9 @@ extern "C" {
  * populations that may already be overwritten, so each step is a psi pass
  * (Q S read, one psi value written per node) and the update (2 Q S plus the
  * psi stencil): about 1.5x the traffic of the A-B pattern for half its
- * population memory.  Results equal those of the A-B pattern.  Not
- * available with locally shifted storage (PLBM_F16R, PLBM_BF16R). */
+ * population memory.  Results equal those of the A-B pattern, in every
+ * storage format (with locally shifted storage the psi pass also writes the
+ * nodes' new reference densities). */
 #define PLBM_PATTERN_AA 1
 /* boundary kinds, per axis */
 #define PLBM_PERIODIC 0

@@ -147,6 +147,12 @@ __global__ __launch_bounds__(TX* TY) void k_aa_psi(const KParams* __restrict__ P
   aa_neighbour_offsets<L, T>(gx, gy, nx, ny, kp->nxb, oxy);
   C* const psi = reinterpret_cast<C*>(kp->psi);
   const uint32_t own = (uint32_t)(gy * nx + gx), plane = (uint32_t)(nx * ny);
+  // locally shifted storage: a node's populations are decoded with its own
+  // reference density (its density one step earlier); the new one is written
+  // for the update's encoder and the next step's decoder
+  constexpr bool LOC = St::local;
+  const RefT* const ref_src = LOC ? reinterpret_cast<const RefT*>(kp->ref[par]) : nullptr;
+  RefT* const ref_dst = LOC ? reinterpret_cast<RefT*>(kp->ref[par ^ 1]) : nullptr;
   auto load = [&](int z, T* v) {
     const int zm = z == 0 ? (WALLS ? 0 : nz - 1) : z - 1;
     const int zp = z == nz - 1 ? (WALLS ? nz - 1 : 0) : z + 1;
@@ -154,11 +160,19 @@ __global__ __launch_bounds__(TX* TY) void k_aa_psi(const KParams* __restrict__ P
                           WALLS && z == 0, WALLS && z == nz - 1, v);
   };
   auto store = [&](int z, const T* v) {
-    C r = aa_dec<St>(v[0], shift[0]);
+    const uint32_t n = (uint32_t)z * plane + own;
+    C rs = 0;
+    if constexpr (LOC) rs = (C)ref_src[n];
+    auto dsh = [&](int i) -> C {
+      if constexpr (LOC) return (C)L::w[i] * rs;
+      else return shift[i];
+    };
+    C r = aa_dec<St>(v[0], dsh(0));
 #pragma unroll
-    for (int i = 1; i < Q; ++i) r += aa_dec<St>(v[i], shift[i]);
+    for (int i = 1; i < Q; ++i) r += aa_dec<St>(v[i], dsh(i));
     bool ng;
-    psi[(uint32_t)z * plane + own] = psi_eval<C>(eos, (double)r, &ng);
+    psi[n] = psi_eval<C>(eos, (double)r, &ng);
+    if constexpr (LOC) ref_dst[n] = (RefT)r;
   };
 #if PLBM_PSI_PF
   // the loads of plane z + 1 are in flight while plane z is summed
@@ -201,7 +215,9 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
   constexpr int QS = Lines<T>::template slots<Q>();
   constexpr uint32_t TS = sizeof(T);
 
-  __shared__ C lds_psi[4 * PL];  // 4-plane psi ring
+  constexpr bool LOC = St::local;
+  __shared__ C lds_psi[4 * PL];                 // 4-plane psi ring
+  __shared__ C lds_ref[LOC ? 4 * PL : 1];       // reference densities (locally shifted storage), same ring
   __shared__ RedRec red_lds[(MODE == MODE_REDUCE) ? NT : 1];
 
   AaTile tl;
@@ -264,14 +280,27 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
     bool d_;
     psw_hi = psi_eval<C>(eos, kp->rho_wall[1], &d_);
   }
+  // locally shifted storage: own populations decode with the node's previous
+  // density (ref_src); f*_i(x) encodes with the new density of the node that
+  // decodes it next step, x + c_i (x itself where it bounces off a wall),
+  // written by the psi pass (ref_dst) and staged into LDS with psi
+  const RefT* const ref_src = LOC ? reinterpret_cast<const RefT*>(kp->ref[par]) : nullptr;
+  const RefT* const ref_dst = LOC ? reinterpret_cast<const RefT*>(kp->ref[par ^ 1]) : nullptr;
   auto stage_psi = [&](int zl) {
-    const C* src = psi + (uint32_t)wrapz(zl) * plane;
+    const uint32_t pz = (uint32_t)wrapz(zl) * plane;
+    const C* src = psi + pz;
     C* sl = lds_psi + ((zl - z0 + 1) & 3) * PL;
     const bool ghost = WALLS && ((zl < 0 && wet_lo) || (zl >= nz && wet_hi));
     const C gv = zl < 0 ? psw_lo : psw_hi;
 #pragma unroll
     for (int k = 0; k < 2; ++k)
       if (pact[k]) sl[t + k * NT] = ghost ? gv : src[po[k]];
+    if constexpr (LOC) {
+      C* rl = lds_ref + ((zl - z0 + 1) & 3) * PL;
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        if (pact[k]) rl[t + k * NT] = (C)ref_dst[pz + po[k]];
+    }
   };
   auto load = [&](int z, T* v) {
     const int zm = z == 0 ? (WALLS ? 0 : nz - 1) : z - 1;
@@ -298,8 +327,10 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
 
   auto update = [&](int z, const T* v) {
     C f[Q];
+    C rs = 0;  // a ragged-tile lane reads a spare reference slot
+    if constexpr (LOC) rs = (C)ref_src[ivalid ? (uint32_t)z * plane + own : (uint32_t)N + ((uint32_t)t & 255u)];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = aa_dec<St>(v[i], shift[i]);
+    for (int i = 0; i < Q; ++i) f[i] = aa_dec<St>(v[i], LOC ? (C)L::w[i] * rs : shift[i]);
     C rho = f[0];
 #pragma unroll
     for (int i = 1; i < Q; ++i) rho += f[i];
@@ -333,9 +364,24 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
       char* bm = A + (uint64_t)zm * zblock;
       char* bp = A + (uint64_t)zp * zblock;
       const bool lo = WALLS && z == 0, hi = WALLS && z == nz - 1;
+      // encoding shift of f*_i(x)
+      const C* r_m = lds_ref + ((z - z0) & 3) * PL;
+      const C* r_0 = lds_ref + ((z - z0 + 1) & 3) * PL;
+      const C* r_p = lds_ref + ((z - z0 + 2) & 3) * PL;
+      auto esh = [&](int i) -> C {
+        if constexpr (LOC) {
+          const int cz = L::cz[i];
+          const C* rr = cz < 0 ? r_m : (cz > 0 ? r_p : r_0);
+          C rd = rr[ilds + L::cx[i] + L::cy[i] * W2];
+          if (WALLS && cz != 0) rd = (cz > 0 ? hi : lo) ? r_0[ilds] : rd;
+          return (C)L::w[i] * rd;
+        } else {
+          return shift[i];
+        }
+      };
       if (par == 0) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) gst<T>(b0 + L::opp[i] * QB, oxy[4], St::enc(fs[i], shift[i]));
+        for (int i = 0; i < Q; ++i) gst<T>(b0 + L::opp[i] * QB, oxy[4], St::enc(fs[i], esh(i)));
       } else {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -343,7 +389,7 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
           const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
           char* b = (cz > 0 ? bp : (cz < 0 ? bm : b0)) + i * QB;
           const uint32_t off = oxy[(1 - cx) + 3 * (1 - cy)];
-          const T e = St::enc(fs[i], shift[i]);
+          const T e = St::enc(fs[i], esh(i));
           if (WALLS && cz != 0) {
             const bool bounce = cz > 0 ? hi : lo;
             gst<T>(bounce ? b0 + L::opp[i] * QB : b, bounce ? oxy[4] : off, e);

@@ -118,8 +118,6 @@ int make_layout(const plbm_lattice_desc* d, Layout* L, int64_t resident = 0) {
     if (d->rho_wall[k] > 0.0 && d->bc[d->lattice == PLBM_D2Q9 ? 1 : 2] != PLBM_HALFWAY_BB)
       return set_error(PLBM_E_INVALID, "a wall density needs walls on the last axis");
   }
-  if (aa && local_shift(d->storage))
-    return set_error(PLBM_E_UNSUPPORTED, "the in-place pattern has no locally shifted storage form");
   const bool is2d = d->lattice == PLBM_D2Q9;
   if (is2d && d->nz != 1) return set_error(PLBM_E_INVALID, "D2Q9 requires nz = 1");
   for (int a = 0; a < 3; ++a)

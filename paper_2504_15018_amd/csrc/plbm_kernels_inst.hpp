@@ -13,20 +13,15 @@ namespace plbm {
 #define PLBM_LDS_PAD 0  // extra LDS bytes per workgroup (limits workgroups per CU)
 #endif
 
-// In-place pattern: the psi pass, then the update (locally shifted storage
-// has no in-place form).
+// In-place pattern: the psi pass, then the update.
 template <class L, int COLL, int MODE, bool WALLS>
 static hipError_t go_aa(const StepLaunch& a) {
   using TS = TileShape<L>;
-  if constexpr (PLBM_ST::local) {
-    return hipErrorInvalidValue;
-  } else {
-    hipLaunchKernelGGL((k_aa_psi<L, PLBM_ST, TS::TX, TS::TY, WALLS>), dim3((uint32_t)a.nblocks * (uint32_t)a.psplit),
-                       dim3(TS::TX * TS::TY), 0, a.stream, a.P, a.work, a.nwork, a.phase, a.psplit);
-    hipLaunchKernelGGL((k_aa_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, WALLS>), dim3(a.nblocks),
-                       dim3(TS::TX * TS::TY), 0, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
-    return hipGetLastError();
-  }
+  hipLaunchKernelGGL((k_aa_psi<L, PLBM_ST, TS::TX, TS::TY, WALLS>), dim3((uint32_t)a.nblocks * (uint32_t)a.psplit),
+                     dim3(TS::TX * TS::TY), 0, a.stream, a.P, a.work, a.nwork, a.phase, a.psplit);
+  hipLaunchKernelGGL((k_aa_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, WALLS>), dim3(a.nblocks),
+                     dim3(TS::TX * TS::TY), 0, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
+  return hipGetLastError();
 }
 
 template <class L, int COLL, int MODE>
@@ -56,11 +51,9 @@ hipError_t PLBM_CAT(launch_step_, PLBM_SUFFIX)(const StepLaunch& a) {
 template <class L, int COLL, bool WALLS>
 static hipError_t occ_go(int aa, int* blocks) {
   using TS = TileShape<L>;
-  if constexpr (!PLBM_ST::local) {
-    if (aa)
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          blocks, k_aa_step<L, PLBM_ST, COLL, MODE_STEP, TS::TX, TS::TY, WALLS>, TS::TX * TS::TY, 0);
-  }
+  if (aa)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        blocks, k_aa_step<L, PLBM_ST, COLL, MODE_STEP, TS::TX, TS::TY, WALLS>, TS::TX * TS::TY, 0);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
       blocks, k_step<L, PLBM_ST, COLL, MODE_STEP, TS::TX, TS::TY, TS::NT, WALLS>, TS::NT, PLBM_LDS_PAD);
 }

@@ -162,10 +162,10 @@ def test_inplace_pattern_bytes_and_validation():
         # one population array less (with a trash area of at most 40 KiB per
         # z plane for ragged-tile lanes), one psi array more
         assert 19 * n * S - n * C <= saved <= 19 * n * S - n * C + 40 * 40 * 1024 + (1 << 20)
-    for st in ("f16r", "bf16r"):
-        with pytest.raises(N.PlbmError) as ei:
-            N.plbm_lattice_bytes(make_desc("D3Q19", (16, 16, 16), storage=st, pattern="aa"))
-        assert ei.value.code == N.PLBM_E_UNSUPPORTED
+    for st in ("f16r", "bf16r"):  # one population array; the two reference-density arrays stay
+        ab = N.plbm_lattice_bytes(make_desc("D3Q19", (64, 48, 40), storage=st))
+        aa = N.plbm_lattice_bytes(make_desc("D3Q19", (64, 48, 40), storage=st, pattern="aa"))
+        assert 19 * n * 2 - n * 4 <= ab - aa <= 19 * n * 2 - n * 4 + 40 * 40 * 1024 + (1 << 20)
     bad = make_desc("D2Q9", (8, 8))
     bad.pattern = 7
     with pytest.raises(N.PlbmError) as ei:

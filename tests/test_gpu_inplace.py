@@ -7,8 +7,8 @@
 * Against the A-B pattern: the two patterns run the same density sum, psi,
   force and collision arithmetic on the same values, so populations, moments
   and reductions must agree bitwise after any number of steps (both time
-  parities, the graph path for n >= 8) and in every storage type that has an
-  in-place form.
+  parities, the graph path for n >= 8) and in every storage type, the locally
+  shifted ones included.
 * In a continuous batch mixed with A-B lattices: bitwise equal to solo runs.
 """
 import numpy as np
@@ -71,6 +71,9 @@ BITWISE = [
     ("D3Q19", (36, 18, 12), "mrt", "f16s", True),
     ("D3Q19", (40, 20, 10), "bgk", "bf16s", False),
     ("D2Q9", (96, 40), "mrt", "bf16s", True),
+    ("D3Q19", (70, 19, 13), "mrt", "f16r", True),
+    ("D3Q19", (33, 17, 12), "bgk", "bf16r", False),
+    ("D2Q9", (131, 40), "mrt", "f16r", False),
 ]
 
 
@@ -122,6 +125,7 @@ def test_inplace_in_a_batch_matches_solo_bitwise():
         ("D3Q19", (40, 24, 18), "mrt", "f32", False, "ab"),
         ("D3Q19", (33, 17, 12), "bgk", "f64", True, "aa"),
         ("D2Q9", (150, 40), "bgk", "f32", False, "aa"),
+        ("D3Q19", (36, 18, 12), "mrt", "f16r", True, "aa"),
     ]
     prm = lib_params(tau_v=0.9, tau_l=1.1)
 
