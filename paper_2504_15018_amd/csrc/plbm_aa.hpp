@@ -109,10 +109,6 @@ __device__ __forceinline__ typename St::C aa_dec(typename St::T v, typename St::
   else return (typename St::C)v;
 }
 
-#ifndef PLBM_PSI_PF
-#define PLBM_PSI_PF 0  // software prefetch of the next plane in the psi pass
-#endif
-
 // psi(rho(x, t)) of every node of a tile's z chunk into kp->psi.  The chunk
 // is split over `split` workgroups (the update's tiling gives about one
 // workgroup per CU, too few for a pass that only streams populations in).
@@ -174,25 +170,11 @@ __global__ __launch_bounds__(TX* TY) void k_aa_psi(const KParams* __restrict__ P
     psi[n] = psi_eval<C>(eos, (double)r, &ng);
     if constexpr (LOC) ref_dst[n] = (RefT)r;
   };
-#if PLBM_PSI_PF
-  // the loads of plane z + 1 are in flight while plane z is summed
-  T va[Q], vb[Q];
-  int z = tl.z0;
-  if (z < tl.z1) load(z, va);
-  for (; z + 1 < tl.z1; z += 2) {
-    load(z + 1, vb);
-    store(z, va);
-    if (z + 2 < tl.z1) load(z + 2, va);
-    store(z + 1, vb);
-  }
-  if (z < tl.z1) store(z, va);
-#else
   for (int z = tl.z0; z < tl.z1; ++z) {
     T v[Q];
     load(z, v);
     store(z, v);
   }
-#endif
 }
 
 // The in-place update (MODE_STEP), or the moments / reductions of the
