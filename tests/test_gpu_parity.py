@@ -243,3 +243,33 @@ def test_graph_replay_matches_single_launches():
     assert np.array_equal(a.populations(), b.populations())
     a.close()
     b.close()
+
+
+def test_c3_64cubed_200_steps_against_the_oracle():
+    """The C3 problem at 64^3 (droplet R = 12, W = 5, float32 MRT + Guo, Peng-Robinson T/Tc = 0.8) for 200
+    steps against the FP64 oracle, at the float32 bars (2e-6 relative per step on f and rho, 1e-6 absolute per
+    step on u)."""
+    require_gpu()
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("c3_64cubed_200")
+    n, steps = 64, 200
+    dims = (n, n, n)
+    op = oracle_params("D3Q19", collision="mrt")
+    co = syn.grid(dims)
+    rho0 = syn.droplet(co, dims, op.rho_v, op.rho_l, R=12.0, W=5.0)
+    lat = Lattice("D3Q19", dims, lib_params(), collision="mrt", storage="f32")
+    lat.init_fields(rho0)
+    f0 = lat.populations()  # the float32 equilibrium as stored: the oracle starts from the same values
+    lat.step(steps)
+    f_ref = S.run(op, f0, steps)
+    tf, tu = 2e-6 * steps, 1e-6 * steps
+    f = lat.populations()
+    err = rel_max(f, f_ref)
+    rho, u = lat.moments()
+    rho_ref, u_ref = S.moments(op, f_ref)
+    fmt("c3_64cubed_200_err", rel_f=f"{err:.2e}", rel_rho=f"{rel_max(rho, rho_ref):.2e}",
+        abs_u=f"{abs_max(u, u_ref):.2e}")
+    assert err <= tf
+    assert rel_max(rho, rho_ref) <= tf
+    assert abs_max(u, u_ref) <= tu
+    lat.close()
