@@ -648,6 +648,7 @@ struct plbm_batch {
   hipStream_t stream;
   KParams* slots_dev;
   WorkItem* work_dev;
+  char* red_dev;  // max_slots final reduction records
   std::vector<plbm_lattice*> lat;
   struct Group {
     int lattice, coll, storage, walls, aa;
@@ -664,10 +665,14 @@ struct plbm_batch {
 
 namespace {
 
-uint64_t batch_layout(int max_slots, int64_t max_tiles, uint64_t* off_work) {
+// Batch device buffer: the slots' kernel parameters, the work table, and one
+// final reduction record per slot.
+uint64_t batch_layout(int max_slots, int64_t max_tiles, uint64_t* off_work, uint64_t* off_red) {
   uint64_t off = align_up((uint64_t)max_slots * sizeof(KParams));
   *off_work = off;
   off = align_up(off + (uint64_t)max_tiles * sizeof(WorkItem));
+  *off_red = off;
+  off = align_up(off + (uint64_t)max_slots * sizeof(RedRec));
   return off;
 }
 
@@ -691,7 +696,10 @@ int batch_rebuild(plbm_batch* b) {
   std::map<std::tuple<int, int, int, int, int>, std::vector<int>> by_type;
   for (int s = 0; s < b->max_slots; ++s) {
     plbm_lattice* L = b->lat[s];
-    if (!L) continue;
+    if (!L) {
+      b->slots_host[s] = KParams{};  // no lattice: ntiles = 0, never dereferenced
+      continue;
+    }
     KParams k = L->kp;
     k.parity = (int)(L->t & 1);
     b->slots_host[s] = k;
@@ -752,8 +760,8 @@ extern "C" {
 
 int plbm_batch_bytes(int32_t max_slots, int64_t max_tiles, uint64_t* bytes) {
   if (max_slots < 1 || max_tiles < 1 || !bytes) return set_error(PLBM_E_INVALID, "bad batch sizes");
-  uint64_t ow;
-  *bytes = batch_layout(max_slots, max_tiles, &ow);
+  uint64_t ow, orr;
+  *bytes = batch_layout(max_slots, max_tiles, &ow, &orr);
   return PLBM_OK;
 }
 
@@ -761,8 +769,8 @@ int plbm_batch_create(int32_t max_slots, int64_t max_tiles, void* dev_mem, uint6
                       plbm_batch** out) {
   if (!out || max_slots < 1 || max_tiles < 1 || !dev_mem) return set_error(PLBM_E_INVALID, "bad batch arguments");
   if (((uintptr_t)dev_mem) % kAlign) return set_error(PLBM_E_INVALID, "device memory must be 256-byte aligned");
-  uint64_t ow;
-  uint64_t need = batch_layout(max_slots, max_tiles, &ow);
+  uint64_t ow, orr;
+  uint64_t need = batch_layout(max_slots, max_tiles, &ow, &orr);
   if (dev_bytes < need) return set_error(PLBM_E_NOMEM, "batch needs %llu bytes", (unsigned long long)need);
   plbm_batch* b = new plbm_batch();
   b->max_slots = max_slots;
@@ -771,6 +779,7 @@ int plbm_batch_create(int32_t max_slots, int64_t max_tiles, void* dev_mem, uint6
   b->stream = static_cast<hipStream_t>(hip_stream);
   b->slots_dev = reinterpret_cast<KParams*>(b->mem);
   b->work_dev = reinterpret_cast<WorkItem*>(b->mem + ow);
+  b->red_dev = b->mem + orr;
   b->lat.assign(max_slots, nullptr);
   b->slots_host.assign(max_slots, KParams{});
   b->g = 0;
@@ -854,14 +863,10 @@ int plbm_batch_diag(plbm_batch* b, plbm_diag* per_slot) {
   std::memset(per_slot, 0, sizeof(plbm_diag) * b->max_slots);
   st = batch_launch(b, MODE_REDUCE, (int)(b->g & 1));
   if (st) return st;
+  // one launch combines every slot's tile records, one copy brings them back
   std::vector<RedRec> recs(b->max_slots);
-  for (int s = 0; s < b->max_slots; ++s) {
-    plbm_lattice* L = b->lat[s];
-    if (!L) continue;
-    RedRec* fin = reinterpret_cast<RedRec*>(L->mem + L->lay.red) + L->lay.ntiles;
-    HIPCHK(launch_reduce_final(b->stream, L->kp_dev, L->lay.ntiles, fin));
-    HIPCHK(hipMemcpyAsync(&recs[s], fin, sizeof(RedRec), hipMemcpyDeviceToHost, b->stream));
-  }
+  HIPCHK(launch_reduce_final_batch(b->stream, b->slots_dev, b->max_slots, b->red_dev));
+  HIPCHK(hipMemcpyAsync(recs.data(), b->red_dev, sizeof(RedRec) * b->max_slots, hipMemcpyDeviceToHost, b->stream));
   HIPCHK(hipStreamSynchronize(b->stream));
   for (int s = 0; s < b->max_slots; ++s)
     if (b->lat[s]) fill_diag(b->lat[s], recs[s], &per_slot[s]);

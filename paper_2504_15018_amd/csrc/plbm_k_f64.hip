@@ -17,11 +17,9 @@ __device__ __forceinline__ void red_combine(RedRec& o, const RedRec& q) {
   o.flags = (double)((int)o.flags | (int)q.flags);
 }
 
-__global__ __launch_bounds__(256) void k_reduce_final(const KParams* __restrict__ P, int ntiles,
-                                                      RedRec* __restrict__ out) {
+__device__ __forceinline__ void reduce_tiles(const RedRec* __restrict__ r, int ntiles, RedRec* __restrict__ out) {
   __shared__ RedRec sh[256];
   const int t = threadIdx.x;
-  const RedRec* r = reinterpret_cast<const RedRec*>(P->red);
   RedRec o;
   o.mass_s = o.mass_c = 0.0;
   o.mom[0] = o.mom[1] = o.mom[2] = 0.0;
@@ -37,8 +35,27 @@ __global__ __launch_bounds__(256) void k_reduce_final(const KParams* __restrict_
   if (t == 0) *out = sh[0];
 }
 
+__global__ __launch_bounds__(256) void k_reduce_final(const KParams* __restrict__ P, int ntiles,
+                                                      RedRec* __restrict__ out) {
+  reduce_tiles(reinterpret_cast<const RedRec*>(P->red), ntiles, out);
+}
+
+// One workgroup per batch slot: the same fixed-order combination for every
+// attached lattice at once (slots without a lattice have ntiles = 0 and give
+// a zero record).
+__global__ __launch_bounds__(256) void k_reduce_final_batch(const KParams* __restrict__ P,
+                                                            RedRec* __restrict__ out) {
+  const KParams* kp = P + blockIdx.x;
+  reduce_tiles(reinterpret_cast<const RedRec*>(kp->red), kp->ntiles, out + blockIdx.x);
+}
+
 hipError_t launch_reduce_final(hipStream_t st, const KParams* P, int ntiles, void* out) {
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, P, ntiles, reinterpret_cast<RedRec*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_final_batch(hipStream_t st, const KParams* P, int nslots, void* out) {
+  hipLaunchKernelGGL(k_reduce_final_batch, dim3(nslots), dim3(256), 0, st, P, reinterpret_cast<RedRec*>(out));
   return hipGetLastError();
 }
 

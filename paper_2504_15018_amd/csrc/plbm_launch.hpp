@@ -108,5 +108,6 @@ hipError_t occupancy_step_bf16r(int lattice, int coll, int walls, int aa, int* b
 hipError_t launch_accum(hipStream_t st, int nblocks, int64_t N, int first, const double* in, double* acc);
 hipError_t launch_set_ref(hipStream_t st, int nblocks, const KParams* P, int par, const double* acc);
 hipError_t launch_reduce_final(hipStream_t st, const KParams* P, int ntiles, void* out);
+hipError_t launch_reduce_final_batch(hipStream_t st, const KParams* P, int nslots, void* out);
 
 }  // namespace plbm
