@@ -273,3 +273,26 @@ def test_c3_64cubed_200_steps_against_the_oracle():
     assert rel_max(rho, rho_ref) <= tf
     assert abs_max(u, u_ref) <= tu
     lat.close()
+
+
+@pytest.mark.parametrize("lattice,dims,walls", [("D2Q9", (70, 37), True), ("D3Q19", (37, 21, 13), False)])
+def test_custom_mrt_rates_match_the_oracle(lattice, dims, walls):
+    """plbm_lattice_desc.mrt_rates = (s_e, s_eps, s_q, s_m), four distinct values, float64 (bar 1e-12): a swapped
+    or dropped rate class fails."""
+    require_gpu()
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("custom_mrt_rates", lattice=lattice)
+    rates = (1.3, 0.7, 1.5, 0.9)
+    f0 = random_state(lattice, dims, 13)
+    op = oracle_params(lattice, collision="mrt", walls=walls, tau_v=0.9, tau_l=1.2,
+                       rates={"e": rates[0], "eps": rates[1], "q": rates[2], "m": rates[3], "j": 1.0, "rho": 1.0})
+    lat = Lattice(lattice, dims, lib_params(tau_v=0.9, tau_l=1.2), collision="mrt", storage="f64", walls=walls,
+                  mrt_rates=rates)
+    lat.write_populations(f0)
+    lat.step(4)
+    f_ref = S.run(op, f0, 4)
+    assert rel_max(lat.populations(), f_ref) <= 1e-12
+    # and the defaults differ measurably, so the rates are really in effect
+    op_default = oracle_params(lattice, collision="mrt", walls=walls, tau_v=0.9, tau_l=1.2)
+    assert rel_max(S.run(op_default, f0, 4), f_ref) > 1e-6
+    lat.close()
