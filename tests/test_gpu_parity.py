@@ -296,3 +296,39 @@ def test_custom_mrt_rates_match_the_oracle(lattice, dims, walls):
     op_default = oracle_params(lattice, collision="mrt", walls=walls, tau_v=0.9, tau_l=1.2)
     assert rel_max(S.run(op_default, f0, 4), f_ref) > 1e-6
     lat.close()
+
+
+@pytest.mark.parametrize("lattice,dims,collision,storage", [("D2Q9", (70, 37), "bgk", "f64"),
+                                                            ("D3Q19", (37, 21, 13), "mrt", "f64"),
+                                                            ("D3Q19", (35, 17, 10), "mrt", "f32")])
+def test_paper_eos_step_matches_the_oracle(lattice, dims, collision, storage):
+    """The paper's own EOS (eq. EOS with K from eq. thickness; R134a-like lattice densities 0.0375 / 1.187,
+    interface width xi = 3) stepped against the oracle, on the usual float64 / float32 bars."""
+    require_gpu()
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+    from oracle import eos as E
+    fmt("paper_eos_parity", lattice=lattice, storage=storage)
+    rv, rl, xi = 0.0375, 1.187, 3.0
+    prm = N.plbm_params_paper_lattice(rv, rl, xi, 2.0, 1.0, 0.8, 1.1)
+    lat_ = LATTICES[lattice]
+    co = syn.grid(dims)
+    rho = syn.droplet(co, dims, rv, rl, R=min(dims) / 3.0, W=2.0 * xi, centre=[n / 2.0 - 0.3 for n in dims])
+    f0 = syn.random_populations(lat_.Q, co, dims, 21, rho, 0.2)
+    op = S.StepParams(lat_, E.PaperEOS(prm.K, prm.eos_rho_v, prm.eos_rho_l), eps=prm.epsilon, kappa=prm.kappa,
+                      G=prm.G, tau_v=prm.tau_v, tau_l=prm.tau_l, rho_v=prm.rho_v, rho_l=prm.rho_l,
+                      collision=collision)
+    lat = Lattice(lattice, dims, prm, collision=collision, storage=storage)
+    lat.write_populations(f0)
+    if storage == "f32":
+        f0 = f0.astype(np.float32).astype(np.float64)
+    steps = 4
+    lat.step(steps)
+    f_ref = S.run(op, f0, steps)
+    tf, tu = (1e-12, 1e-12) if storage == "f64" else (2e-6 * steps, 1e-6 * steps)
+    assert rel_max(lat.populations(), f_ref) <= tf
+    rho_g, u = lat.moments()
+    rho_r, u_r = S.moments(op, f_ref)
+    assert rel_max(rho_g, rho_r) <= tf
+    assert abs_max(u, u_r) <= tu
+    lat.close()
