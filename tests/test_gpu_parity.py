@@ -41,6 +41,8 @@ CASES = [
     ("D3Q19", (33, 35, 9), "mrt", "f64", False, 3, {"kappa": 0.7, "tau_v": 1.1, "tau_l": 0.9}),
     ("D3Q19", (35, 17, 10), "mrt", "f32", False, 3, {}),
     ("D3Q19", (32, 16, 12), "bgk", "f32", True, 3, {"Fg": (1e-5, 0.0, 0.0)}),
+    ("D2Q9", (64, 40), "mrt", "f64", False, 5, {"eps": 1.3, "kappa": 1.4}),
+    ("D3Q19", (33, 18, 11), "bgk", "f64", True, 4, {"eps": 1.0}),
 ]
 
 
