@@ -334,3 +334,28 @@ def test_paper_eos_step_matches_the_oracle(lattice, dims, collision, storage):
     assert rel_max(rho_g, rho_r) <= tf
     assert abs_max(u, u_r) <= tu
     lat.close()
+
+
+@pytest.mark.parametrize("pattern", ["ab", "aa"])
+def test_moments_device_equals_host_read_out(pattern):
+    """plbm_moments_device writes the same float64 rho and u (SoA) into caller device buffers as
+    plbm_read_moments returns on the host, at both time parities."""
+    require_gpu()
+    import torch
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("moments_device", pattern=pattern)
+    dims = (37, 21, 13)
+    lat = Lattice("D3Q19", dims, lib_params(Fg=(1e-5, 0.0, 0.0)), collision="mrt", storage="f32", pattern=pattern)
+    lat.write_populations(random_state("D3Q19", dims, 31))
+    for n in (3, 4):
+        lat.step(n)
+        rho_h, u_h = lat.moments()
+        rho_d = torch.full((lat.N,), float("nan"), dtype=torch.float64, device="cuda")
+        u_d = torch.full((3, lat.N), float("nan"), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()  # the fill runs on torch's stream, the read-out on the lattice's
+        N.plbm_moments_device(lat.h, rho_d.data_ptr(), u_d.data_ptr())
+        lat.stream.synchronize()
+        assert np.array_equal(rho_d.cpu().numpy().reshape(rho_h.shape), rho_h)
+        assert np.array_equal(u_d.cpu().numpy().reshape(u_h.shape), u_h)
+    lat.close()
