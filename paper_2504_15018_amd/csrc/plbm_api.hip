@@ -269,13 +269,21 @@ int aux_blocks(int64_t N) {
 
 // Workgroups per tile chunk of the in-place pattern's psi pass (measured on
 // 256^3: float32 and float64 fastest with one, 16-bit storage with eight;
-// PLBM_PSI_SPLIT overrides, for tuning).
+// PLBM_PSI_SPLIT overrides, for tuning; read once).
 int psi_split(int storage) {
-  if (const char* e = std::getenv("PLBM_PSI_SPLIT")) {
-    int v = std::atoi(e);
-    if (v > 0) return v;
-  }
+  static const int forced = [] {
+    const char* e = std::getenv("PLBM_PSI_SPLIT");
+    return e ? std::atoi(e) : 0;
+  }();
+  if (forced > 0) return forced;
   return storage_bytes(storage) == 2 ? 8 : 1;
+}
+
+// Multi-step calls replay captured two-step graphs unless PLBM_NO_GRAPH is set
+// (read once).
+bool graphs_enabled() {
+  static const bool on = std::getenv("PLBM_NO_GRAPH") == nullptr;
+  return on;
 }
 
 int run_step_kernel(plbm_lattice* L, int mode, int phase, double* orho, double* ou) {
@@ -507,7 +515,7 @@ int plbm_step(plbm_lattice* L, int64_t n) {
   if (n < 0) return set_error(PLBM_E_INVALID, "negative step count");
   // long runs replay a captured two-step graph; short ones launch directly
   // (the legacy null stream cannot be captured)
-  if (n >= 8 && L->stream != nullptr && !std::getenv("PLBM_NO_GRAPH")) {
+  if (n >= 8 && L->stream != nullptr && graphs_enabled()) {
     int st = capture_graph2(L);
     if (st) return st;
     if (L->t & 1) {
@@ -821,7 +829,7 @@ int plbm_batch_step(plbm_batch* b, int64_t n) {
   if (st) return st;
   if (b->groups.empty()) return PLBM_OK;
   const int64_t n0 = n;
-  if (n >= 4 && b->stream != nullptr && !std::getenv("PLBM_NO_GRAPH")) {
+  if (n >= 4 && b->stream != nullptr && graphs_enabled()) {
     if (!b->has_graph) {
       hipGraph_t gr;
       HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
