@@ -239,7 +239,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--collision", default="mrt", choices=["mrt", "bgk"])
-    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16s", "bf16s"])
+    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16s", "bf16s", "f16r", "bf16r"])
     ap.add_argument("--pattern", default="ab", choices=["ab", "aa"],
                     help="population storage pattern: two arrays (ab) or in place (aa)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -318,11 +318,14 @@ def main():
     nodes = lat.N
     ms_per_step = wall * 1e3 / K
     mlups = nodes * K / wall / 1e6
-    S = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[args.storage]
+    S = {"f64": 8, "f32": 4}.get(args.storage, 2)
+    # locally shifted storage also reads and writes a 2-byte reference density per node (twice in place: the
+    # psi pass writes the new one, the update reads it for the encoder)
+    R = 0 if args.storage in ("f64", "f32", "f16s", "bf16s") else 2
     if args.pattern == "aa":  # psi pass (Q S read, C written) + in-place update (2 Q S, C of psi read)
-        bytes_per_launch = (3 * 19 * S + 2 * (8 if args.storage == "f64" else 4)) * nodes
+        bytes_per_launch = (3 * 19 * S + 2 * (8 if args.storage == "f64" else 4) + 4 * R) * nodes
     else:
-        bytes_per_launch = 2 * 19 * S * nodes
+        bytes_per_launch = (2 * 19 * S + 2 * R) * nodes
     achieved = bytes_per_launch / avg_kernel_s / 1e9
     dfin = lat.reduce()
     log(f"[bench] {K} steps in {wall:.3f} s; step kernel avg {avg_kernel_s * 1e3:.4f} ms; "
