@@ -45,13 +45,12 @@ __device__ __forceinline__ bool aa_tile(int wid, const KParams* __restrict__ P, 
   }
   const KParams* __restrict__ kp = P + slot;
   if (tile >= kp->ntiles) return false;
-  const int tiles_x = kp->tiles_x, tiles_y = kp->tiles_y;
+  int txi, tyi;
+  tile_extent(kp, tile, &txi, &tyi, &o->z0, &o->z1);
   o->kp = kp;
   o->tile = tile;
-  o->x0 = (tile % tiles_x) * TX;
-  o->y0 = ((tile / tiles_x) % tiles_y) * TY;
-  o->z0 = (tile / (tiles_x * tiles_y)) * kp->cz;
-  o->z1 = min(o->z0 + kp->cz, kp->nz);
+  o->x0 = txi * TX;
+  o->y0 = tyi * TY;
   return true;
 }
 
@@ -119,7 +118,8 @@ __global__ __launch_bounds__(TX* TY) void k_aa_psi(const KParams* __restrict__ P
   using C = typename St::C;
   constexpr int Q = L::Q;
   // consecutive (tile, sub-chunk) items share an XCD, as in the update
-  const int item = xcd_remap(blockIdx.x, gridDim.x);
+  const int item =
+      work != nullptr ? xcd_remap(blockIdx.x, gridDim.x) : class_remap(blockIdx.x, gridDim.x, P->ntl * split);
   AaTile tl;
   if (!aa_tile(item / split, P, work, nwork, TX, TY, &tl)) return;
   const KParams* __restrict__ kp = tl.kp;
@@ -141,14 +141,14 @@ __global__ __launch_bounds__(TX* TY) void k_aa_psi(const KParams* __restrict__ P
   for (int i = 0; i < Q; ++i) shift[i] = (C)(L::w[i] * kp->rho0_shift);
   uint32_t oxy[9];
   aa_neighbour_offsets<L, T>(gx, gy, nx, ny, kp->nxb, oxy);
-  C* const psi = reinterpret_cast<C*>(kp->psi);
+  void* const psi = kp->psi;
   const uint32_t own = (uint32_t)(gy * nx + gx), plane = (uint32_t)(nx * ny);
   // locally shifted storage: a node's populations are decoded with its own
   // reference density (its density one step earlier); the new one is written
   // for the update's encoder and the next step's decoder
   constexpr bool LOC = St::local;
-  const RefT* const ref_src = LOC ? reinterpret_cast<const RefT*>(kp->ref[par]) : nullptr;
-  RefT* const ref_dst = LOC ? reinterpret_cast<RefT*>(kp->ref[par ^ 1]) : nullptr;
+  const void* const ref_src = LOC ? kp->ref[par] : nullptr;
+  void* const ref_dst = LOC ? kp->ref[par ^ 1] : nullptr;
   auto load = [&](int z, T* v) {
     const int zm = z == 0 ? (WALLS ? 0 : nz - 1) : z - 1;
     const int zp = z == nz - 1 ? (WALLS ? nz - 1 : 0) : z + 1;
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(TX* TY) void k_aa_psi(const KParams* __restrict__ P
   auto store = [&](int z, const T* v) {
     const uint32_t n = (uint32_t)z * plane + own;
     C rs = 0;
-    if constexpr (LOC) rs = (C)ref_src[n];
+    if constexpr (LOC) rs = (C)gld_at<RefT>(ref_src, n);
     auto dsh = [&](int i) -> C {
       if constexpr (LOC) return (C)L::w[i] * rs;
       else return shift[i];
@@ -167,8 +167,8 @@ __global__ __launch_bounds__(TX* TY) void k_aa_psi(const KParams* __restrict__ P
 #pragma unroll
     for (int i = 1; i < Q; ++i) r += aa_dec<St>(v[i], dsh(i));
     bool ng;
-    psi[n] = psi_eval<C>(eos, (double)r, &ng);
-    if constexpr (LOC) ref_dst[n] = (RefT)r;
+    gst_at<C>(psi, n, psi_eval<C>(eos, (double)r, &ng));
+    if constexpr (LOC) gst_at<RefT>(ref_dst, n, (RefT)r);
   };
   for (int z = tl.z0; z < tl.z1; ++z) {
     T v[Q];
@@ -203,7 +203,8 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
   __shared__ RedRec red_lds[(MODE == MODE_REDUCE) ? NT : 1];
 
   AaTile tl;
-  if (!aa_tile(xcd_remap(blockIdx.x, gridDim.x), P, work, nwork, TX, TY, &tl)) return;  // whole workgroup
+  const int wid = work != nullptr ? xcd_remap(blockIdx.x, gridDim.x) : class_remap(blockIdx.x, gridDim.x, P->ntl);
+  if (!aa_tile(wid, P, work, nwork, TX, TY, &tl)) return;  // whole workgroup
   const KParams* __restrict__ kp = tl.kp;
   const int nx = kp->nx, ny = kp->ny, nz = kp->nz;
   const int x0 = tl.x0, y0 = tl.y0, z0 = tl.z0, z1 = tl.z1;
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
   const uint32_t zdata = (uint32_t)kp->zdata;
   const int par = (phase + kp->parity) & 1;
   char* const A = reinterpret_cast<char*>(kp->pop[0]);
-  const C* const psi = reinterpret_cast<const C*>(kp->psi);
+  const void* const psi = kp->psi;
   const EosK eos = load_eos(kp);
   C shift[Q];
 #pragma unroll
@@ -266,22 +267,21 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
   // density (ref_src); f*_i(x) encodes with the new density of the node that
   // decodes it next step, x + c_i (x itself where it bounces off a wall),
   // written by the psi pass (ref_dst) and staged into LDS with psi
-  const RefT* const ref_src = LOC ? reinterpret_cast<const RefT*>(kp->ref[par]) : nullptr;
-  const RefT* const ref_dst = LOC ? reinterpret_cast<const RefT*>(kp->ref[par ^ 1]) : nullptr;
+  const void* const ref_src = LOC ? kp->ref[par] : nullptr;
+  const void* const ref_dst = LOC ? kp->ref[par ^ 1] : nullptr;
   auto stage_psi = [&](int zl) {
     const uint32_t pz = (uint32_t)wrapz(zl) * plane;
-    const C* src = psi + pz;
     C* sl = lds_psi + ((zl - z0 + 1) & 3) * PL;
     const bool ghost = WALLS && ((zl < 0 && wet_lo) || (zl >= nz && wet_hi));
     const C gv = zl < 0 ? psw_lo : psw_hi;
 #pragma unroll
     for (int k = 0; k < 2; ++k)
-      if (pact[k]) sl[t + k * NT] = ghost ? gv : src[po[k]];
+      if (pact[k]) sl[t + k * NT] = ghost ? gv : gld_at<C>(psi, pz + po[k]);
     if constexpr (LOC) {
       C* rl = lds_ref + ((zl - z0 + 1) & 3) * PL;
 #pragma unroll
       for (int k = 0; k < 2; ++k)
-        if (pact[k]) rl[t + k * NT] = (C)ref_dst[pz + po[k]];
+        if (pact[k]) rl[t + k * NT] = (C)gld_at<RefT>(ref_dst, pz + po[k]);
     }
   };
   auto load = [&](int z, T* v) {
@@ -302,7 +302,8 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
   C rate[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) rate[k] = (C)kp->rates[k];
-  float* const uprev = kp->uprev;
+  typedef __attribute__((address_space(1))) float gfloat;  // global_load/store, not flat
+  gfloat* const uprev = (gfloat*)kp->uprev;
 
   double acc_ms = 0.0, acc_mc = 0.0, acc_mom[3] = {0.0, 0.0, 0.0}, acc_umax = 0.0, acc_dumax = 0.0;
   int acc_flags = 0;
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
   auto update = [&](int z, const T* v) {
     C f[Q];
     C rs = 0;  // a ragged-tile lane reads a spare reference slot
-    if constexpr (LOC) rs = (C)ref_src[ivalid ? (uint32_t)z * plane + own : (uint32_t)N + ((uint32_t)t & 255u)];
+    if constexpr (LOC) rs = (C)gld_at<RefT>(ref_src, ivalid ? (uint32_t)z * plane + own : (uint32_t)N + ((uint32_t)t & 255u));
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = aa_dec<St>(v[i], LOC ? (C)L::w[i] * rs : shift[i]);
     C rho = f[0];
@@ -396,7 +397,7 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
           const double ua = (double)u[a];
           acc_mom[a] += dr * ua;
           usq += ua * ua;
-          float* up = uprev + (size_t)a * N + nid;
+          gfloat* up = uprev + (size_t)a * N + nid;
           const double dd = ua - (double)*up;
           dsq += dd * dd;
           *up = (float)ua;

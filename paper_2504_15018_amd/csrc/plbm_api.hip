@@ -61,6 +61,7 @@ struct Layout {
   int Q, D;
   int nxk, nyk, nzk;  // kernel axes
   int tx, ty, cz, tiles_x, tiles_y, tiles_z, ntiles;
+  int cz2, ncl, ntl;  // two-class z partition (see choose_partition)
   int nxb;         // 128-byte x blocks per row of stored populations
   uint64_t zdata;  // bytes of node data of one z plane of stored populations
   uint64_t zblock; // zdata plus a trash area for the ragged-tile lanes of one workgroup
@@ -75,32 +76,77 @@ bool local_shift(int storage) { return storage == PLBM_F16R || storage == PLBM_B
 // workgroups / resident rounds, where `resident` is how many step workgroups
 // the device holds at once (CUs times the occupancy of the kernel).  A
 // partly filled last round costs about half a round more than its share
-// (measured on the 256^3 cube and the 384x384x128 channel), so the chunk
-// minimises (workgroups / resident + ceil(workgroups / resident)) (cz + 2);
-// on ties the longer chunk.  Without a device (resident <= 0), aim at 512
-// workgroups.
-int choose_cz(int nzk, int tiles_xy, int64_t resident) {
+// (measured on the 256^3 cube and the 384x384x128 channel), so a uniform
+// chunk costs (workgroups / resident + ceil(workgroups / resident)) / 2 (cz + 2)
+// plane times; the chunk minimises that, on ties the longer chunk.  Without
+// a device (resident <= 0), aim at 512 workgroups.
+struct ZPart {
+  int cz;   // planes per chunk of the first ncl columns (whole columns when ncl > 0)
+  int cz2;  // planes per chunk of the other columns
+  int ncl;  // columns split with cz; 0 for a uniform partition with cz2
+};
+
+static double uniform_cost(int nzk, int64_t cols, int cz, int64_t resident) {
+  const int64_t wg = cols * ((nzk + cz - 1) / cz);
+  return 0.5 * ((double)wg / resident + (double)((wg + resident - 1) / resident)) * (cz + 2);
+}
+
+static int best_uniform(int nzk, int64_t cols, int64_t resident, double* cost) {
+  int best = nzk;
+  double bc = -1.0;
+  for (int cz = nzk; cz >= 1 && cz >= (nzk < 4 ? 1 : 4); --cz) {
+    const double c = uniform_cost(nzk, cols, cz, resident);
+    if (bc < 0.0 || c < bc) {
+      bc = c;
+      best = cz;
+    }
+  }
+  *cost = bc;
+  return best;
+}
+
+// Two classes of work items when a lattice has more columns (tiles_xy) than
+// the device holds workgroups: the first m * resident columns as whole
+// columns (m rounds in which every workgroup ends together, no partial
+// round), then the remaining columns in shorter chunks that fill the last
+// round (launched in that order, so the long items start first).  On the
+// 384x384x128 channel (288 columns of 64 x 8 nodes, 256 resident) that is
+// 256 whole columns plus 32 columns in chunks of 16 planes, 148 plane times
+// against 161.5 for the best uniform chunk (32 planes, 4.5 rounds).
+ZPart choose_partition(int nzk, int tiles_xy, int64_t resident) {
+  ZPart z{0, 0, 0};
   if (const char* e = std::getenv("PLBM_CZ")) {
     int v = std::atoi(e);
-    if (v > 0) return v < nzk ? v : nzk;
+    if (v > 0) {
+      z.cz = z.cz2 = v < nzk ? v : nzk;
+      return z;
+    }
   }
   if (resident <= 0) {
     int64_t cz = ((int64_t)nzk * tiles_xy + 511) / 512;
     if (cz < 4) cz = 4;
     if (cz > 128) cz = 128;
-    return (int)(cz > nzk ? nzk : cz);
+    z.cz = z.cz2 = (int)(cz > nzk ? nzk : cz);
+    return z;
   }
-  int best = nzk;
-  int64_t best_cost = -1;
-  for (int cz = nzk; cz >= 1 && cz >= (nzk < 4 ? 1 : 4); --cz) {
-    const int64_t wg = (int64_t)tiles_xy * ((nzk + cz - 1) / cz);
-    const int64_t cost = (wg + resident * ((wg + resident - 1) / resident)) * (int64_t)(cz + 2);
-    if (best_cost < 0 || cost < best_cost) {
-      best_cost = cost;
-      best = cz;
+  double best;
+  z.cz = z.cz2 = best_uniform(nzk, tiles_xy, resident, &best);
+  const char* u = std::getenv("PLBM_UNIFORM_CHUNKS");
+  if (u && std::atoi(u) != 0) return z;
+  for (int64_t m = 1; m * resident <= tiles_xy; ++m) {
+    const int64_t rest = tiles_xy - m * resident;
+    double c2 = 0.0;
+    int cz2 = nzk;
+    if (rest > 0) cz2 = best_uniform(nzk, rest, resident, &c2);
+    const double c = (double)m * (nzk + 2) + c2;
+    if (c < best) {
+      best = c;
+      z.cz = nzk;
+      z.cz2 = cz2;
+      z.ncl = (int)(m * resident);
     }
   }
-  return best;
+  return z;
 }
 
 int make_layout(const plbm_lattice_desc* d, Layout* L, int64_t resident = 0) {
@@ -141,9 +187,15 @@ int make_layout(const plbm_lattice_desc* d, Layout* L, int64_t resident = 0) {
   }
   L->tiles_x = (L->nxk + L->tx - 1) / L->tx;
   L->tiles_y = (L->nyk + L->ty - 1) / L->ty;
-  L->cz = choose_cz(L->nzk, L->tiles_x * L->tiles_y, resident);
-  L->tiles_z = (L->nzk + L->cz - 1) / L->cz;
-  int64_t nt = (int64_t)L->tiles_x * L->tiles_y * L->tiles_z;
+  {
+    const ZPart zp = choose_partition(L->nzk, L->tiles_x * L->tiles_y, resident);
+    L->cz = zp.cz;
+    L->cz2 = zp.cz2;
+    L->ncl = zp.ncl;
+  }
+  L->tiles_z = (L->nzk + L->cz2 - 1) / L->cz2;  // chunks per column of the second class
+  L->ntl = L->ncl * ((L->nzk + L->cz - 1) / L->cz);
+  int64_t nt = (int64_t)L->ntl + (int64_t)(L->tiles_x * L->tiles_y - L->ncl) * L->tiles_z;
   if ((int64_t)L->tiles_x * L->tiles_y * L->nzk > 0x3fffffff) return set_error(PLBM_E_INVALID, "too many tiles");
   L->ntiles = (int)nt;
   // reduction records are sized for the shortest chunk, so that the byte
@@ -351,6 +403,9 @@ void fill_kparams(plbm_lattice* L) {
   k.tiles_y = y.tiles_y;
   k.tiles_z = y.tiles_z;
   k.cz = y.cz;
+  k.cz2 = y.cz2;
+  k.ncl = y.ncl;
+  k.ntl = y.ntl;
   k.ntiles = y.ntiles;
   k.eos = p.eos;
   k.K = p.K;

@@ -227,6 +227,10 @@ struct KParams {
   int32_t nx, ny, nz; // kernel axes (2-D lattices: ny = 1)
   int32_t bb_z;       // half-way bounce-back walls on the marching axis
   int32_t tiles_x, tiles_y, tiles_z, cz;  // tiling: tiles per axis, planes per z chunk
+  // z partition in two classes: items [0, ntl) split the first ncl tile
+  // columns into chunks of cz planes, the other items the remaining columns
+  // into chunks of cz2 (ncl = ntl = 0: one uniform class of cz2)
+  int32_t cz2, ncl, ntl;
   int32_t ntiles;
   int32_t eos;
   // paper EOS: p = K [2 r^3 + (rv - 2 rl) r^2 + sqrt(rv) sqrt(r) (-3 r^2 + 2 rl r + rl^2)]

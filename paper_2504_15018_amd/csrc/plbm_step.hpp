@@ -67,6 +67,35 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return (b & 7) * (nfull >> 3) + (b >> 3);
 }
 
+// Launch index -> work item of a single-lattice launch whose first ntl items
+// (the long chunks of the two-class z partition) must start first: each class
+// is XCD-remapped within itself, so the first ntl launch indices stay in the
+// long class.
+__device__ __forceinline__ int class_remap(int b, int nb, int ntl) {
+  if (ntl <= 0 || ntl >= nb) return xcd_remap(b, nb);
+  return b < ntl ? xcd_remap(b, ntl) : ntl + xcd_remap(b - ntl, nb - ntl);
+}
+
+// Tile column and z range of work item `tile` of a lattice.
+__device__ __forceinline__ void tile_extent(const KParams* __restrict__ kp, int tile, int* txi, int* tyi, int* z0,
+                                            int* z1) {
+  const int tiles_x = kp->tiles_x, ncl = kp->ncl, ntl = kp->ntl;
+  int col, cz;
+  if (tile < ntl) {
+    col = tile % ncl;
+    cz = kp->cz;
+    *z0 = (tile / ncl) * cz;
+  } else {
+    const int r = tile - ntl, nc = tiles_x * kp->tiles_y - ncl;
+    col = ncl + r % nc;
+    cz = kp->cz2;
+    *z0 = (r / nc) * cz;
+  }
+  *txi = col % tiles_x;
+  *tyi = col / tiles_x;
+  *z1 = min(*z0 + cz, kp->nz);
+}
+
 // Loads and stores through a scalar (wave-uniform) base pointer in the global
 // address space plus a 32-bit byte offset: global_load/store with an SGPR
 // base.  The library keeps every per-direction array below 4 GiB.
@@ -75,6 +104,20 @@ __device__ __forceinline__ T gld(const void* base, uint32_t byte_off) {
   typedef const __attribute__((address_space(1))) char gchar;
   typedef const __attribute__((address_space(1))) T gT;
   return *(gT*)((gchar*)base + byte_off);
+}
+
+// Element access to a per-node array (psi, reference densities) through a
+// global-address-space pointer: global_load/store rather than flat, whose
+// completion the LDS counter also waits for.
+template <class T>
+__device__ __forceinline__ T gld_at(const void* base, uint32_t idx) {
+  typedef const __attribute__((address_space(1))) T gT;
+  return ((gT*)base)[idx];
+}
+template <class T>
+__device__ __forceinline__ void gst_at(void* base, uint32_t idx, T v) {
+  typedef __attribute__((address_space(1))) T gT;
+  ((gT*)base)[idx] = v;
 }
 
 #ifndef PLBM_NT_STORE
@@ -285,7 +328,7 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   __shared__ C lds_ref[LOC ? 4 * PL + 64 : 1];  // reference densities, same ring
   __shared__ RedRec red_lds[(MODE == MODE_REDUCE) ? NT : 1];
 
-  int wid = xcd_remap(blockIdx.x, gridDim.x);
+  int wid = work != nullptr ? xcd_remap(blockIdx.x, gridDim.x) : class_remap(blockIdx.x, gridDim.x, P->ntl);
   int slot = 0, tile = wid;
   if (work != nullptr) {
     if (wid >= nwork) return;
@@ -300,12 +343,9 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   const int nxb = kp->nxb;
   const uint64_t zblock = (uint64_t)kp->zblock;  // bytes of one z plane of stored populations
   const uint32_t zdata = (uint32_t)kp->zdata;    // bytes of its node data (a trash area follows)
-  const int tiles_x = kp->tiles_x, tiles_y = kp->tiles_y, czc = kp->cz;
-  const int txi = tile % tiles_x;
-  const int tyi = (tile / tiles_x) % tiles_y;
-  const int tzi = tile / (tiles_x * tiles_y);
-  const int x0 = txi * TX, y0 = tyi * TY, z0 = tzi * czc;
-  const int z1 = min(z0 + czc, nz);
+  int txi, tyi, z0, z1;
+  tile_extent(kp, tile, &txi, &tyi, &z0, &z1);
+  const int x0 = txi * TX, y0 = tyi * TY;
   const int par = (phase + kp->parity) & 1;
   char* const pop0 = reinterpret_cast<char*>(kp->pop[0]);
   char* const pop1 = reinterpret_cast<char*>(kp->pop[1]);
@@ -458,8 +498,9 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     for (int i = 1; i < Q; ++i) r += decode(f, i, ref);
     return r;
   };
-  const RefT* const ref_src = LOC ? reinterpret_cast<const RefT*>(kp->ref[par]) : nullptr;
-  RefT* const ref_dst = LOC ? reinterpret_cast<RefT*>(kp->ref[par ^ 1]) : nullptr;
+  const void* const ref_src = LOC ? kp->ref[par] : nullptr;
+  void* const ref_dst = LOC ? kp->ref[par ^ 1] : nullptr;
+  auto ref_ld = [&](uint32_t n) -> RefT { return gld_at<RefT>(ref_src, n); };
 
   bool psi_neg = false;
 
@@ -480,8 +521,8 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     pull(ioxy, bm, b0, bp, lo, hi, fo);
     if constexpr (HALO) pull(hoxy, bm, b0, bp, lo, hi, ho);
     if constexpr (LOC) {
-      qo = ref_src[(uint32_t)(pz * plane + own)];
-      if constexpr (HALO) qh = ref_src[(uint32_t)(pz * plane + hown)];
+      qo = ref_ld((uint32_t)(pz * plane + own));
+      if constexpr (HALO) qh = ref_ld((uint32_t)(pz * plane + hown));
     }
   };
   auto as_ref = [&](RefT v) -> C {
@@ -519,7 +560,8 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   C rate[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) rate[k] = (C)kp->rates[k];
-  float* const uprev = kp->uprev;
+  typedef __attribute__((address_space(1))) float gfloat;  // global_load/store, not flat
+  gfloat* const uprev = (gfloat*)kp->uprev;
 
   // reduction accumulators
   double acc_ms = 0.0, acc_mc = 0.0, acc_mom[3] = {0.0, 0.0, 0.0}, acc_umax = 0.0, acc_dumax = 0.0;
@@ -575,7 +617,7 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
         // ragged-tile lanes write one of the 256 spare slots after the N
         // nodes (never read; a tile has up to 1024 threads)
         const uint32_t ridx = ivalid ? nid : (uint32_t)N + ((uint32_t)t & 255u);
-        ref_dst[ridx] = (RefT)rho;
+        gst_at<RefT>(ref_dst, ridx, (RefT)rho);
       } else {
 #pragma unroll
         for (int i = 0; i < Q; ++i) gst<T>(dz + i * QB, soff, St::enc(fs[i], shift[i]));
@@ -596,7 +638,7 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
           const double ua = (double)u[a];
           acc_mom[a] += dr * ua;
           usq += ua * ua;
-          float* up = uprev + (size_t)a * N + nid;
+          gfloat* up = uprev + (size_t)a * N + nid;
           const double dd = ua - (double)*up;
           dsq += dd * dd;
           *up = (float)ua;
@@ -697,7 +739,7 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
       const int zp = pz == nz - 1 ? (WALLS ? nz - 1 : 0) : pz + 1;
       pull(hoxy, src + (uint64_t)zm * zblock, src + (uint64_t)pz * zblock, src + (uint64_t)zp * zblock,
            WALLS && pz == 0, WALLS && pz == nz - 1, ho);
-      if constexpr (LOC) qh = ref_src[(uint32_t)(pz * plane + hown)];
+      if constexpr (LOC) qh = ref_ld((uint32_t)(pz * plane + hown));
     };
     auto hfinish = [&](int zl, const R* ho, RefT qh) {
       const int slot = ((zl - z0 + 1) & 3) * PL;
