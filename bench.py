@@ -22,6 +22,11 @@ same workload on the host (one single-threaded process per core, aggregated).
 array; a psi pass and the in-place update per step).  Its roofline covers the
 two launches of a step together: 3 Q S + 2 C bytes per node (C = 4 bytes,
 the psi value, 8 for float64) over the step's duration.
+
+`--precision` runs the precision form instead: the 384 x 384 x 128 channel
+in every storage format (coexistence densities and u_x profile against the
+float64 run), then static droplets (D2Q9 512^2, D3Q19 128^3; densities,
+Laplace jump and spurious currents against float64).
 """
 import argparse
 import json
@@ -155,6 +160,49 @@ def copy_probe(torch, nbytes=2 << 30, reps=20):
                       "copy_GBps_read_plus_write": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
 
 
+PR_OMEGA = 0.326  # acentric factor of the paper's fluid
+
+
+def droplet_precision_run(N, Lattice, lattice, n, R, steps, tr=0.8):
+    """Static droplet (MRT, periodic) in every storage format: the Laplace jump p_EOS(centre) - p_EOS(far
+    field), the droplet radius from its equivalent area or volume, the spurious-current maximum max|u| and
+    the densities at the centre and in the far field, each against the float64 run."""
+    import numpy as np
+
+    def pr_pressure(prm, r):  # Peng-Robinson in the lattice parameters the library resolved
+        b = prm.pr_b
+        return r * prm.pr_R * prm.pr_T / (1.0 - b * r) - prm.pr_a * prm.pr_alpha * r * r / (1.0 + 2.0 * b * r - b * b * r * r)
+
+    prm = N.plbm_params_pr_lattice(tr, PR_OMEGA, 2.0, 1.0, 1.0, 1.0)
+    dims = (n, n) if lattice == "D2Q9" else (n, n, n)
+    centre = [n / 2.0] * len(dims)
+    rows = {}
+    for st in ["f64", "f32", "f16s", "bf16s", "f16r", "bf16r"]:
+        lat = Lattice(lattice, dims, prm, collision="mrt", storage=st)
+        lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=5.0, R=R, centre=centre)
+        lat.step(steps)
+        rho, u = lat.moments()
+        d = lat.reduce(allow_unstable=True)
+        lat.close()
+        mid = tuple(n // 2 for _ in dims)
+        r_in, r_out = float(rho[mid]), float(rho[(0,) * len(dims)])
+        frac = float(np.sum((rho - r_out) / (r_in - r_out)))
+        radius = np.sqrt(frac / np.pi) if lattice == "D2Q9" else (3.0 * frac / (4.0 * np.pi)) ** (1.0 / 3.0)
+        dp = pr_pressure(prm, r_in) - pr_pressure(prm, r_out)
+        rows[st] = {"rho_in": r_in, "rho_out": r_out, "laplace_jump": dp, "radius": float(radius),
+                    "spurious_max_u": float(np.sqrt((u ** 2).sum(axis=0)).max()), "flags": d.flags}
+        log(f"[precision] {lattice} droplet {st}: dp {dp:.6e}, max|u| {rows[st]['spurious_max_u']:.3e}, flags {d.flags}")
+    ref = rows["f64"]
+    for st, r in rows.items():
+        r["rho_in_rel_err"] = abs(r["rho_in"] - ref["rho_in"]) / ref["rho_in"]
+        r["rho_out_rel_err"] = abs(r["rho_out"] - ref["rho_out"]) / ref["rho_out"]
+        r["laplace_jump_rel_err"] = abs(r["laplace_jump"] - ref["laplace_jump"]) / abs(ref["laplace_jump"])
+        r["spurious_max_u_rel_err"] = abs(r["spurious_max_u"] - ref["spurious_max_u"]) / ref["spurious_max_u"]
+    name = f"{n}^2" if lattice == "D2Q9" else f"{n}^3"
+    return {"workload": f"{lattice} static droplet {name} periodic, R = {R:g}, tanh width 5, PR T/Tc = {tr}, MRT, "
+                        f"{steps} steps", "storages": rows}
+
+
 def precision_run(torch, N, Lattice, steps):
     """Layered channel between plates, 384 x 384 x 128 (walls on z, F_g = 1e-6 x, BGK tau = 1), in every
     storage format; coexistence densities and the u_x profile against the float64 run."""
@@ -248,6 +296,9 @@ def main():
     ap.add_argument("--precision", action="store_true",
                     help="storage-format comparison on the 384x384x128 channel instead of the step benchmark")
     ap.add_argument("--precision-steps", type=int, default=20000)
+    ap.add_argument("--precision-droplets", type=int, default=1,
+                    help="with --precision: also the Laplace jump and spurious currents of static droplets "
+                         "(D2Q9 512^2, D3Q19 128^3) by storage format (0 skips them)")
     ap.add_argument("--serve", action="store_true", help="serving-loop run instead of the step benchmark")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-budget-gb", type=float, default=240.0)
@@ -268,8 +319,12 @@ def main():
         return
     N.load()
     if args.precision:
-        print(json.dumps({"metric": "coexistence density error vs float64 by storage format",
-                          **precision_run(torch, N, Lattice, args.precision_steps)}), flush=True)
+        out = {"metric": "coexistence density error vs float64 by storage format",
+               **precision_run(torch, N, Lattice, args.precision_steps)}
+        if args.precision_droplets:
+            out["droplets"] = [droplet_precision_run(N, Lattice, "D2Q9", 512, 64.0, 20000),
+                               droplet_precision_run(N, Lattice, "D3Q19", 128, 32.0, 10000)]
+        print(json.dumps(out), flush=True)
         return
     if args.serve:
         print(json.dumps({"metric": "solves/s + p50/p99 time to converged solution",
