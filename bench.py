@@ -291,6 +291,8 @@ def main():
     ap.add_argument("--pattern", default="ab", choices=["ab", "aa"],
                     help="population storage pattern: two arrays (ab) or in place (aa)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--u0", type=float, default=0.0,
+                    help="uniform initial velocity along x (0.05: the Galilean-invariance variant of the droplet)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain device-to-device copy of 2 GiB (HBM reference for the roofline)")
     ap.add_argument("--precision", action="store_true",
@@ -337,7 +339,8 @@ def main():
     log(f"[bench] coexistence rho_v={prm.rho_v:.6f} rho_l={prm.rho_l:.6f}")
     lat = Lattice("D3Q19", dims, prm, collision=args.collision, storage=args.storage, pattern=args.pattern)
     R = 48.0 * n / 256.0
-    lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=5.0, R=R, centre=[n / 2.0] * 3)
+    lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=5.0, R=R, centre=[n / 2.0] * 3,
+                   u0=(args.u0, 0.0, 0.0))
     stream = lat.stream
     log(f"[bench] lattice {dims} D3Q19 {args.collision} {args.storage} pattern {args.pattern}, "
         f"{lat.nbytes / 2**30:.2f} GiB; "
@@ -376,11 +379,11 @@ def main():
     S = {"f64": 8, "f32": 4}.get(args.storage, 2)
     # locally shifted storage also reads and writes a 2-byte reference density per node (twice in place: the
     # psi pass writes the new one, the update reads it for the encoder)
-    R = 0 if args.storage in ("f64", "f32", "f16s", "bf16s") else 2
+    RB = 0 if args.storage in ("f64", "f32", "f16s", "bf16s") else 2
     if args.pattern == "aa":  # psi pass (Q S read, C written) + in-place update (2 Q S, C of psi read)
-        bytes_per_launch = (3 * 19 * S + 2 * (8 if args.storage == "f64" else 4) + 4 * R) * nodes
+        bytes_per_launch = (3 * 19 * S + 2 * (8 if args.storage == "f64" else 4) + 4 * RB) * nodes
     else:
-        bytes_per_launch = (2 * 19 * S + 2 * R) * nodes
+        bytes_per_launch = (2 * 19 * S + 2 * RB) * nodes
     achieved = bytes_per_launch / avg_kernel_s / 1e9
     dfin = lat.reduce()
     log(f"[bench] {K} steps in {wall:.3f} s; step kernel avg {avg_kernel_s * 1e3:.4f} ms; "
@@ -408,7 +411,8 @@ def main():
         "config": {"workload": f"D3Q19 static droplet {n}^3 periodic, {args.storage} populations"
                                f"{' (in place)' if args.pattern == 'aa' else ''}, "
                                f"{args.collision.upper()} + Guo forcing, Peng-Robinson T/Tc=0.8, radius {R:g}, "
-                               f"tanh width 5; reduction every {REDUCE_EVERY} steps",
+                               f"tanh width 5{f', uniform initial u_x = {args.u0:g}' if args.u0 else ''}; "
+                               f"reduction every {REDUCE_EVERY} steps",
                    "lattice": "D3Q19", "nodes": nodes, "storage": args.storage, "collision": args.collision,
                    "pattern": args.pattern, "lattice_bytes": lat.nbytes,
                    "parallelism": "single GPU"},
