@@ -163,6 +163,43 @@ def copy_probe(torch, nbytes=2 << 30, reps=20):
 PR_OMEGA = 0.326  # acentric factor of the paper's fluid
 
 
+def stream_probe(torch, nodes=256 ** 3, reps=50):
+    """Reference rates of the population access pattern on this GPU (libplbm_probe.so): 19 float32 arrays in
+    the blocked population layout read and written once per launch (the update's algorithmic bytes with no
+    halo, stencil or collision), and a plain float4 copy of the same bytes."""
+    import ctypes
+    lib_path = os.path.join(ROOT, "paper_2504_15018_amd", "libplbm_probe.so")
+    if not os.path.exists(lib_path):
+        raise RuntimeError(f"{lib_path} is not built: run `python -m paper_2504_15018_amd.build`")
+    lib = ctypes.CDLL(lib_path)
+    lib.plbm_probe_stream19.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]
+    lib.plbm_probe_copy4.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+    nfl = 19 * 32 * ((nodes + 31) // 32)
+    a = torch.ones(nfl, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(st.cuda_stream)
+
+    def timed(fn):
+        for _ in range(3):
+            if fn() != 0:
+                raise RuntimeError("probe launch failed")
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    moved = 2 * 19 * 4 * nodes
+    t19 = timed(lambda: lib.plbm_probe_stream19(a.data_ptr(), b.data_ptr(), nodes, sp))
+    tcp = timed(lambda: lib.plbm_probe_copy4(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp))
+    return {"nodes": nodes, "stream19_blocked_us": round(t19 * 1e6, 1), "stream19_blocked_GBps": round(moved / t19 / 1e9, 1),
+            "copy4_us": round(tcp * 1e6, 1), "copy4_GBps_read_plus_write": round(moved / tcp / 1e9, 1)}
+
+
 def droplet_precision_run(N, Lattice, lattice, n, R, steps, tr=0.8):
     """Static droplet (MRT, periodic) in every storage format: the Laplace jump p_EOS(centre) - p_EOS(far
     field), the droplet radius from its equivalent area or volume, the spurious-current maximum max|u| and
@@ -295,6 +332,8 @@ def main():
                     help="uniform initial velocity along x (0.05: the Galilean-invariance variant of the droplet)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain device-to-device copy of 2 GiB (HBM reference for the roofline)")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="reference rates: 19 arrays streamed in the population layout, and a float4 copy")
     ap.add_argument("--precision", action="store_true",
                     help="storage-format comparison on the 384x384x128 channel instead of the step benchmark")
     ap.add_argument("--precision-steps", type=int, default=20000)
@@ -318,6 +357,10 @@ def main():
 
     if args.copy_probe:
         copy_probe(torch)
+        return
+    if args.stream_probe:
+        print(json.dumps({"metric": "reference rates of the population access pattern", **stream_probe(torch)}),
+              flush=True)
         return
     N.load()
     if args.precision:

@@ -85,6 +85,23 @@ def build(jobs=None, verbose=False, out=None, defines=()):
     return lib
 
 
+PROBE_SRC = "probe_stream.hip"
+PROBE_LIB = os.path.join(PKG, "libplbm_probe.so")
+
+
+def build_probe(verbose=False):
+    """Compile the bandwidth probes (the benchmark's reference points) into libplbm_probe.so."""
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [hipcc()] + COMMON + ["-shared", os.path.join(CSRC, PROBE_SRC), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    if verbose:
+        print(f"built {PROBE_LIB}")
+    return PROBE_LIB
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
@@ -92,4 +109,6 @@ if __name__ == "__main__":
     ap.add_argument("-D", dest="defines", action="append", default=[], help="extra preprocessor definition")
     a = ap.parse_args()
     build(a.jobs, verbose=True, out=a.out, defines=a.defines)
+    if a.out is None:
+        build_probe(verbose=True)
     sys.exit(0)

@@ -35,3 +35,13 @@ def test_profiled_traffic_only_for_the_profiled_workload():
     assert bench.profiled_traffic("f32", "mrt", 128) is None
     t = bench.profiled_traffic("f32", "mrt", 256)
     assert t is None or 2.0e9 < t < 4.0e9  # bytes per update launch when the profile matches the sources
+
+
+def test_probe_library_exports_its_two_probes():
+    import ctypes
+    path = os.path.join(ROOT, "paper_2504_15018_amd", "libplbm_probe.so")
+    if not os.path.exists(path):
+        import pytest
+        pytest.skip("libplbm_probe.so not built")
+    lib = ctypes.CDLL(path)
+    assert hasattr(lib, "plbm_probe_stream19") and hasattr(lib, "plbm_probe_copy4")
