@@ -250,15 +250,16 @@ struct KParams {
   int64_t zdata;   // bytes of the node data of one z plane
 };
 
-// Stored population layout: A[z][y][x / XB][q][x % XB] with XB = 32 nodes
-// (16 for float64), so that the innermost unit, one direction of XB nodes, is
-// QB = XB * sizeof(T) bytes: a 128-byte line for float32 and float64, half a
-// line for 16-bit storage.  A block holds QS >= Q direction slots, QS even for
-// 16-bit storage, so every block starts on a line and a 32-wide tile row
-// covers whole lines that no other tile touches.  All directions of a node sit
-// at a common offset plus q * QB bytes.
+// Stored population layout: A[z][y][x / XB][q][x % XB] with XB = 128 bytes /
+// sizeof(T) nodes (16 for float64, 32 for float32, 64 for 16-bit storage), so
+// that the innermost unit, one direction of XB nodes, is one 128-byte line in
+// every format (16-bit blocks of 32 nodes, half a line per direction, ran the
+// update 11 % slower).  A block holds QS >= Q direction slots, so every block
+// starts on a line and a tile row of a multiple of XB nodes covers whole
+// lines that no other tile touches.  All directions of a node sit at a common
+// offset plus q * QB bytes.
 #ifndef PLBM_XB
-#define PLBM_XB 32
+#define PLBM_XB 64
 #endif
 template <class T>
 struct Lines {
