@@ -32,14 +32,15 @@ SOURCES = {
     # issue priority) and tiles 64 nodes wide (the x-halo columns read lines
     # that only the neighbouring tile otherwise uses, so fewer columns per
     # node pay most); float32 and the 16-bit formats 64 x 8 tiles (eleven
-    # waves, three per SIMD, one workgroup per CU), float16 with loads a full
-    # plane iteration ahead, the others one phase ahead; float64 64 x 4 tiles
+    # waves, three per SIMD, one workgroup per CU), the globally shifted 16-bit
+    # formats with loads a full plane iteration ahead, the others one phase
+    # ahead (the locally shifted ones run 17 % slower a full plane ahead); float64 64 x 4 tiles
     # (seven waves within 256 registers).  Populations are stored with the
     # non-temporal hint.
     "plbm_k_f64.hip": ["-ffp-contract=off", "-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=4"],
     "plbm_k_f32.hip": ["-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3"],
     "plbm_k_f16s.hip": ["-DPLBM_PREFETCH=2", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3"],
-    "plbm_k_bf16s.hip": ["-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3"],
+    "plbm_k_bf16s.hip": ["-DPLBM_PREFETCH=2", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3"],
     "plbm_k_f16r.hip": ["-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3"],
     "plbm_k_bf16r.hip": ["-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3"],
     "plbm_api.hip": [],
