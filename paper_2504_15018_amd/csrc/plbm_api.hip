@@ -568,11 +568,22 @@ int plbm_init_shape(plbm_lattice* L, const plbm_shape* s) {
 int plbm_step(plbm_lattice* L, int64_t n) {
   if (check_free(L)) return PLBM_E_INVALID;
   if (n < 0) return set_error(PLBM_E_INVALID, "negative step count");
-  // long runs replay a captured two-step graph; short ones launch directly
-  // (the legacy null stream cannot be captured)
-  if (n >= 8 && L->stream != nullptr && graphs_enabled()) {
-    int st = capture_graph2(L);
-    if (st) return st;
+  // Step pairs replay a captured two-step graph.  It is captured on the
+  // first call (n = 0 included), so no later call pays for capture and
+  // instantiation.  The legacy null stream cannot be captured, and a stream
+  // the caller is capturing takes the launches directly into its own graph.
+  bool replay = false;
+  if (L->stream != nullptr && graphs_enabled()) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHK(hipStreamIsCapturing(L->stream, &cs));
+    if (cs == hipStreamCaptureStatusNone) {
+      int st = capture_graph2(L);
+      if (st) return st;
+      replay = true;
+    }
+  }
+  if (replay && n >= 2) {
+    int st;
     if (L->t & 1) {
       st = run_step_kernel(L, MODE_STEP, 1, nullptr, nullptr);
       if (st) return st;

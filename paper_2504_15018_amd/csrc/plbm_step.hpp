@@ -457,11 +457,17 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     }
   }
 
-  // logical plane zl (may be -1 or nz) -> stored plane
+  // logical plane zl -> stored plane in [0, nz).  The march touches
+  // z0 - 1 <= zl <= z1 only, but a periodic axis may be shorter than that
+  // window (nz = 1 or 2), so it wraps as often as needed; walls clamp.
   auto wrapz = [&](int zl) {
-    if (zl < 0) return WALLS ? 0 : zl + nz;
-    if (zl >= nz) return WALLS ? nz - 1 : zl - nz;
-    return zl;
+    if constexpr (WALLS) {
+      return zl < 0 ? 0 : (zl >= nz ? nz - 1 : zl);
+    } else {
+      while (zl < 0) zl += nz;
+      while (zl >= nz) zl -= nz;
+      return zl;
+    }
   };
 
   // Pull the Q populations of one node of stored plane pz; bm, b0, bp are
@@ -667,12 +673,14 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     finish(halo_c, z0, true, f0, r0, q0, hb, qh);
     issue(halo_c, z0 + 1, f1, hb, q1, qh);
     finish(halo_c, z0 + 1, true, f1, r1, q1, hb, qh);
-    // loads of z+2 into pf, barrier, collide z, psi of z+2
+    // loads of z+2 into pf, barrier, collide z, psi of z+2 (planes past z1
+    // are not needed: the last collided plane, z1 - 1, reads psi up to z1)
     auto stepz = [&](int z, R* cur, C rc, RefT qc, R* pf, C& rp, RefT& qp) {
-      issue(halo_c, z + 2, pf, hb, qp, qh);
+      const bool need = z + 2 <= z1;
+      if (need) issue(halo_c, z + 2, pf, hb, qp, qh);
       __syncthreads();
       phaseB(z, cur, rc, qc);
-      finish(halo_c, z + 2, true, pf, rp, qp, hb, qh);
+      if (need) finish(halo_c, z + 2, true, pf, rp, qp, hb, qh);
     };
     int z = z0;
     for (; z + 2 < z1; z += 3) {
@@ -701,13 +709,15 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     finish(halo_c, z0, true, fa, ra, qa, ha, qha);
     issue(halo_c, z0 + 1, fb, ha, qb, qha);
     finish(halo_c, z0 + 1, true, fb, rb, qb, ha, qha);
-    issue(halo_c, z0 + 2, fc, ha, qc, qha);
+    if (z0 + 2 <= z1) issue(halo_c, z0 + 2, fc, ha, qc, qha);
+    // planes past z1 are neither loaded nor summed (the last collided plane,
+    // z1 - 1, reads psi up to z1)
     auto stepz = [&](int z, R* cur, C rcur, RefT qcur, R* f2, C& r2, RefT& q2, R* h2, RefT& qh2, R* pf, RefT& qp,
                      R* hp, RefT& qhp) {
-      issue(halo_c, z + 3, pf, hp, qp, qhp);
+      if (z + 3 <= z1) issue(halo_c, z + 3, pf, hp, qp, qhp);
       __syncthreads();
       phaseB(z, cur, rcur, qcur);
-      finish(halo_c, z + 2, true, f2, r2, q2, h2, qh2);
+      if (z + 2 <= z1) finish(halo_c, z + 2, true, f2, r2, q2, h2, qh2);
     };
     int z = z0;
     for (; z + 3 < z1; z += 4) {
@@ -753,27 +763,29 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
       hissue(zl, ha, qa);
       hfinish(zl, ha, qa);
     }
+    // as in the tile march, planes past z1 are neither loaded nor summed
     int z = z0;
 #if PLBM_PREFETCH == 1
     for (; z < z1; ++z) {
-      hissue(z + 2, ha, qa);
+      const bool need = z + 2 <= z1;
+      if (need) hissue(z + 2, ha, qa);
       __syncthreads();
-      hfinish(z + 2, ha, qa);
+      if (need) hfinish(z + 2, ha, qa);
     }
 #else
-    hissue(z0 + 2, ha, qa);
+    if (z0 + 2 <= z1) hissue(z0 + 2, ha, qa);
     for (; z + 1 < z1; z += 2) {
-      hissue(z + 3, hb, qb);
+      if (z + 3 <= z1) hissue(z + 3, hb, qb);
       __syncthreads();
-      hfinish(z + 2, ha, qa);
-      hissue(z + 4, ha, qa);
+      if (z + 2 <= z1) hfinish(z + 2, ha, qa);
+      if (z + 4 <= z1) hissue(z + 4, ha, qa);
       __syncthreads();
-      hfinish(z + 3, hb, qb);
+      if (z + 3 <= z1) hfinish(z + 3, hb, qb);
     }
     if (z < z1) {
-      hissue(z + 3, hb, qb);
+      if (z + 3 <= z1) hissue(z + 3, hb, qb);
       __syncthreads();
-      hfinish(z + 2, ha, qa);
+      if (z + 2 <= z1) hfinish(z + 2, ha, qa);
     }
 #endif
   };

@@ -19,7 +19,11 @@ temperature of the lattice Peng-Robinson EOS, droplet radius.  The loop
     memory released at once, so queued requests can take their place.
 
 Every lattice's result is bitwise the same as stepping it alone: the batch
-only changes which workgroup computes which tile.
+only changes which workgroup computes which tile.  With `record_results`, a
+converged lattice's droplet densities (centre and far corner) and maximum
+speed are read on the device before it is released; `solve_alone` runs one
+request by itself on the plain single-lattice path (any storage, e.g. float64)
+to the same convergence test, for comparison with the served result.
 """
 import time
 
@@ -47,6 +51,7 @@ class Request:
         self.slot = None
         self.params = None
         self.error = None
+        self.result = None  # droplet densities and max|u| at convergence (record_results)
 
     @property
     def nodes(self):
@@ -56,7 +61,58 @@ class Request:
         return {"id": self.id, "arrival": self.arrival, "admit": self.admit, "done": self.done,
                 "latency": None if self.done is None else self.done - self.arrival, "steps": self.steps,
                 "status": self.status, "bytes": self.bytes, "nodes": self.nodes, "lattice": self.lattice,
-                "dims": self.dims, "T_over_Tc": self.T_over_Tc, "residual": self.residual, "error": self.error}
+                "dims": self.dims, "T_over_Tc": self.T_over_Tc, "residual": self.residual, "error": self.error,
+                "result": self.result}
+
+
+def droplet_readout(torch, lat, dims, max_u):
+    """Densities at the droplet centre (node dims // 2) and in the far field (node 0), from the moments of the
+    lattice's current state computed on the device; lat's stream must be idle or own the work before it."""
+    n = int(np.prod(dims))
+    d = len(dims)
+    rho = torch.empty(n, dtype=torch.float64, device="cuda")
+    u = torch.empty(d * n, dtype=torch.float64, device="cuda")
+    N.plbm_moments_device(lat.h, rho.data_ptr(), u.data_ptr())
+    lat.stream.synchronize()
+    centre = 0
+    stride = 1
+    for ext in dims:
+        centre += (ext // 2) * stride
+        stride *= ext
+    return {"rho_in": float(rho[centre].item()), "rho_out": float(rho[0].item()), "max_u": float(max_u)}
+
+
+def solve_alone(req, storage="f64", collision="mrt", check_every=100, tol=1e-8, max_steps=2_000_000, width=5.0,
+                time_limit=None):
+    """Run one request alone on the plain single-lattice path (plbm_step / plbm_reduce) until its residual
+    max|u(t) - u(t-k)|/k is at or below tol; returns (status, steps, result)."""
+    import torch
+
+    prm = N.plbm_params_pr_lattice(req.T_over_Tc, 0.326, 2.0, 1.0, 1.0, 1.0)
+    lat = Lattice(req.lattice, req.dims, prm, collision=collision, storage=storage)
+    t0 = time.perf_counter()
+    try:
+        lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=width, R=req.radius,
+                       centre=[n / 2.0 for n in req.dims])
+        lat.reduce()
+        steps, status, d = 0, "capped", None
+        while steps < max_steps:
+            lat.step(check_every)
+            steps += check_every
+            d = lat.reduce(allow_unstable=True)
+            if d.flags & (N.PLBM_FLAG_NAN | N.PLBM_FLAG_RHO_NONPOS):
+                status = "failed"
+                break
+            if d.max_du_per_step <= tol:
+                status = "converged"
+                break
+            if time_limit is not None and time.perf_counter() - t0 > time_limit:
+                status = "timeout"
+                break
+        res = droplet_readout(torch, lat, req.dims, d.max_u if d is not None else 0.0)
+        return status, steps, res
+    finally:
+        lat.close()
 
 
 def admissible(queue, n_resident, used, budget, max_slots):
@@ -109,7 +165,7 @@ class Server:
 
     def __init__(self, budget_bytes, max_slots=64, max_tiles=1 << 20, check_every=100, tol=1e-8,
                  max_steps=2_000_000, storage="f32", collision="bgk", keep_lattices=False, width=5.0,
-                 pattern="ab"):
+                 pattern="ab", record_results=False):
         import torch
 
         self.torch = torch
@@ -123,11 +179,19 @@ class Server:
         self.collision = collision
         self.pattern = pattern  # "aa": in place, about half the population memory per resident lattice
         self.keep = keep_lattices
+        self.record_results = record_results
         self.width = width
         self.lanes = {}
         self.used = 0
         self.peak_used = 0
         self.peak_resident = 0
+        self._cancel = set()
+
+    def cancel(self, rid):
+        """Withdraw request `rid`.  A queued or not yet arrived request is dropped; a resident one is detached
+        and its memory released once its lane's chunk in flight has completed (its kernels may still use the
+        lattice until then).  It ends with status "cancelled"."""
+        self._cancel.add(rid)
 
     def _lane(self, kind):
         if kind not in self.lanes:
@@ -171,7 +235,9 @@ class Server:
         self.peak_used = max(self.peak_used, self.used)
         self.peak_resident = max(self.peak_resident, sum(len(ln.resident) for ln in self.lanes.values()))
 
-    def _retire(self, lane, req, status, now):
+    def _retire(self, lane, req, status, now, max_u=0.0):
+        if status == "converged" and self.record_results:
+            req.result = droplet_readout(self.torch, req.lat, req.dims, max_u)
         N.plbm_batch_detach(lane.batch, req.slot)
         del lane.resident[req.slot]
         req.status = status
@@ -206,12 +272,20 @@ class Server:
             if d.flags & (N.PLBM_FLAG_NAN | N.PLBM_FLAG_RHO_NONPOS):
                 self._retire(lane, req, "failed", now)
             elif req.residual <= self.tol:
-                self._retire(lane, req, "converged", now)
+                self._retire(lane, req, "converged", now, d.max_u)
             elif req.steps >= self.max_steps:
                 self._retire(lane, req, "capped", now)
         lane.inflight = 0
         lane.event = None
         return served
+
+    def _drop_cancelled(self, lane, now):
+        """Cancelled requests of an idle lane: queued ones leave the queue, resident ones are released."""
+        for r in [r for r in lane.queue if r.id in self._cancel]:
+            lane.queue.remove(r)
+            r.status, r.done = "cancelled", now
+        for r in [r for r in lane.resident.values() if r.id in self._cancel]:
+            self._retire(lane, r, "cancelled", now)
 
     # ---- the loop ----
     def run(self, requests, time_limit=None, log=None):
@@ -233,14 +307,20 @@ class Server:
             if time_limit is not None and now > time_limit:
                 break
             while i < len(pending) and pending[i].arrival <= now:
-                self._lane(pending[i].lattice).queue.append(pending[i])
+                r = pending[i]
                 i += 1
+                if r.id in self._cancel:
+                    r.status, r.done = "cancelled", now
+                    continue
+                self._lane(r.lattice).queue.append(r)
             progressed = False
             for lane in self.lanes.values():
                 if lane.inflight and lane.event.query():
                     served_updates += self._check(lane, time.perf_counter() - t0)
                     progressed = True
                 if not lane.inflight:
+                    if self._cancel:
+                        self._drop_cancelled(lane, time.perf_counter() - t0)
                     if lane.queue:
                         self._admit_queue(lane, time.perf_counter() - t0)
                     if lane.resident:
@@ -277,6 +357,7 @@ def summarize(reqs, makespan, served_updates):
         "capped": sum(r.status == "capped" for r in reqs),
         "failed": sum(r.status == "failed" for r in reqs),
         "rejected": sum(r.status == "rejected" for r in reqs),
+        "cancelled": sum(r.status == "cancelled" for r in reqs),
         "unfinished": sum(r.done is None and r.status != "rejected" for r in reqs),
         "makespan_s": makespan,
         "solves_per_s": len(done) / makespan if makespan > 0 else 0.0,

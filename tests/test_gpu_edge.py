@@ -79,3 +79,80 @@ def test_zero_steps_change_nothing(pattern):
     lat.step(0)
     assert lat.time == 3 and np.array_equal(lat.populations(), f3)
     lat.close()
+
+
+SHORT_AXES = [
+    # lattice, dims (the last axis is the kernel's marching axis), steps
+    ("D3Q19", (5, 3, 1), 3),
+    ("D3Q19", (5, 3, 2), 3),
+    ("D3Q19", (4, 3, 3), 4),
+    ("D2Q9", (7, 1), 3),
+    ("D2Q9", (7, 2), 4),
+]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s", "f16r", "bf16r"])
+@pytest.mark.parametrize("case", SHORT_AXES, ids=lambda c: f"{c[0]}-{'x'.join(map(str, c[1]))}")
+def test_short_periodic_marching_axis_reads_stay_inside_the_lattice(case, storage):
+    """A periodic marching axis shorter than the march's load window (one to
+    three planes) must wrap inside the population arrays.  The lattice sits at
+    the start of a buffer whose remaining megabyte holds all-ones bytes (NaN
+    in every storage format): a load past the lattice's own bytes would sum a
+    NaN density, whose psi radicand raises the PSI_NEG flag of the reduction
+    (and NaN populations would break parity).  The state is a smooth +-5 %
+    perturbation, far from the densities where the radicand turns negative,
+    so any flag is a read outside the lattice."""
+    require_gpu()
+    import torch
+
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import make_desc
+    from oracle.lattice import LATTICES
+    from gpu_cases import ULP, storage_round
+
+    lattice, dims, steps = case
+    fmt("edge_short_axis", case=case, storage=storage)
+    op = oracle_params(lattice, collision="mrt")
+    rl = op.rho_l
+    shifted = storage in ("f16s", "bf16s")
+    desc = make_desc(lattice, dims, "mrt", storage, rho0_shift=rl if shifted else 0.0)
+    nb = N.plbm_lattice_bytes(desc)
+    pad = 1 << 20
+    mem = torch.full((nb + 256 + pad,), 0xFF, dtype=torch.uint8, device="cuda")
+    ptr = (mem.data_ptr() + 255) // 256 * 256
+    stream = torch.cuda.Stream()
+    h = N.plbm_create(desc, lib_params(), ptr, nb, stream.cuda_stream)
+    Q = LATTICES[lattice].Q
+    n = int(np.prod(dims))
+    try:
+        f_in = random_state(lattice, dims, 31, rel_amp=0.05)
+        N.plbm_write_populations(h, f_in.reshape(-1))
+        f0 = f_in if storage == "f64" else (f_in.astype(np.float32).astype(np.float64) if storage == "f32"
+                                            else storage_round(lattice, f_in, storage, rl))
+        ref = f0
+        for k in range(steps):
+            d = N.plbm_reduce(h, True)  # both time parities
+            assert d.flags == 0, (k, d.flags)
+            N.plbm_step(h, 1)
+            ref = S.step(op, ref)
+        d = N.plbm_reduce(h, True)
+        assert d.flags == 0, d.flags
+        f = N.plbm_read_populations(h, Q, n).reshape(ref.shape)
+        if storage == "f64":
+            tol = 1e-12
+        elif storage == "f32":
+            tol = 2e-6 * steps
+        else:
+            w = LATTICES[lattice].w.reshape((-1,) + (1,) * len(dims))
+            dev = np.max(np.abs(ref - w * (rl if shifted else ref.sum(axis=0)[None])))
+            tol = steps * (ULP[storage] * dev / np.max(np.abs(ref)) + 2e-6)
+        err = rel_max(f, ref)
+        fmt("edge_short_axis_err", err=f"{err:.3e}", tol=f"{tol:.3e}")
+        assert err <= tol
+        # the bytes after the lattice are untouched
+        stream.synchronize()
+        tail = mem[ptr - mem.data_ptr() + nb:]
+        assert bool((tail == 0xFF).all())
+    finally:
+        stream.synchronize()
+        N.plbm_destroy(h)

@@ -359,3 +359,81 @@ def test_moments_device_equals_host_read_out(pattern):
         assert np.array_equal(rho_d.cpu().numpy().reshape(rho_h.shape), rho_h)
         assert np.array_equal(u_d.cpu().numpy().reshape(u_h.shape), u_h)
     lat.close()
+
+
+RESIDUAL_CASES = [c for c in CASES if c[3] == "f64"][:4] + [c for c in CASES if c[3] == "f32"][:2]
+
+
+@pytest.mark.parametrize("k", [1, 7])
+@pytest.mark.parametrize("case", RESIDUAL_CASES, ids=_ids)
+def test_residual_matches_the_oracle(case, k):
+    """The serving and convergence residual max_x |u(t) - u(t-k)| / k (u including F/2) of plbm_reduce against
+    the oracle's reduce(u_prev, k).  The library keeps u(t-k) in float32: given that same rounded u(t-k), the
+    oracle agrees to float64 rounding (float64 storage; float32 storage to its u bar per step); against the
+    unrounded u(t-k) the difference stays within the float32 floor sqrt(d) max|u(t-k)| 2^-24 / k."""
+    require_gpu()
+    fmt("residual_parity", case=_ids(case), k=k)
+    lattice, dims, collision, storage, walls, steps, extra = case
+    lat, op, f_ref = _run_pair(*case)
+    d0 = lat.reduce()
+    assert d0.max_du_per_step == 0.0  # first reduction: no earlier u
+    ref0, u0 = OD.reduce(op, f_ref)
+    lat.step(k)
+    f_k = S.run(op, f_ref, k)
+    d1 = lat.reduce()
+    ref_exact, _ = OD.reduce(op, f_k, u_prev=u0, dt_prev=k)
+    ref_f32, u1 = OD.reduce(op, f_k, u_prev=u0.astype(np.float32).astype(np.float64), dt_prev=k)
+    r = d1.max_du_per_step
+    # u at both times enters; float32 storage carries its per-step u bar
+    tu = 1e-13 if storage == "f64" else 1e-6 * (steps + k)
+    fmt("residual_parity_vals", lib=f"{r:.6e}", oracle=f"{ref_exact['max_du_per_step']:.6e}",
+        oracle_f32_prev=f"{ref_f32['max_du_per_step']:.6e}")
+    assert abs(r - ref_f32["max_du_per_step"]) <= 2 * tu / k
+    floor = np.sqrt(LATTICES[lattice].d) * float(np.max(np.abs(u0))) * 2.0**-24 / k
+    assert abs(r - ref_exact["max_du_per_step"]) <= floor + 2 * tu / k
+    assert d1.flags == ref_exact["flags"] and d1.time == steps + k
+    # the stride is the library's own time since the last reduction: 2 more steps
+    lat.step(2)
+    f_k2 = S.run(op, f_k, 2)
+    d2 = lat.reduce()
+    ref2, _ = OD.reduce(op, f_k2, u_prev=u1.astype(np.float32).astype(np.float64), dt_prev=2)
+    assert abs(d2.max_du_per_step - ref2["max_du_per_step"]) <= tu
+    lat.close()
+
+
+def test_batch_residual_matches_the_oracle():
+    """plbm_batch_diag's per-slot residual, two float64 lattices of different kinds stepped together."""
+    require_gpu()
+    import torch
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("batch_residual_parity")
+    specs = [CASES[1], CASES[5]]
+    stream = torch.cuda.Stream()
+    nb = N.plbm_batch_bytes(4, 4096)
+    mem = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    b = N.plbm_batch_create(4, 4096, (mem.data_ptr() + 255) // 256 * 256, nb, stream.cuda_stream)
+    lats, ops, fs, slots = [], [], [], []
+    for lattice, dims, collision, storage, walls, steps, extra in specs:
+        f0 = random_state(lattice, dims, 9)
+        op = oracle_params(lattice, collision=collision, walls=walls, **extra)
+        lat = Lattice(lattice, dims, lib_params(**extra), collision=collision, storage=storage, walls=walls,
+                      stream=stream)
+        lat.write_populations(f0)
+        lats.append(lat)
+        ops.append(op)
+        fs.append(f0)
+        slots.append(N.plbm_batch_attach(b, lat.h))
+    N.plbm_batch_diag(b, 4)  # u(0) stored
+    us = [OD.reduce(op, f)[1] for op, f in zip(ops, fs)]
+    k = 5
+    N.plbm_batch_step(b, k)
+    diag = N.plbm_batch_diag(b, 4)
+    for s, op, f, u0 in zip(slots, ops, fs, us):
+        ref, _ = OD.reduce(op, S.run(op, f, k), u_prev=u0.astype(np.float32).astype(np.float64), dt_prev=k)
+        assert abs(diag[s].max_du_per_step - ref["max_du_per_step"]) <= 2e-13 / k
+        assert diag[s].time == k and diag[s].flags == ref["flags"]
+    stream.synchronize()
+    N.plbm_batch_destroy(b)
+    for lat in lats:
+        lat.close()

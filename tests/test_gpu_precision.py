@@ -27,39 +27,9 @@ import pytest
 from oracle import step as S
 from oracle.lattice import LATTICES
 
-from gpu_cases import fmt, lib_params, oracle_params, pr_coex, random_state, rel_max, require_gpu
+from gpu_cases import ULP, fmt, lib_params, oracle_params, pr_coex, random_state, rel_max, require_gpu, storage_round
 
 pytestmark = pytest.mark.gpu
-
-ULP = {"f16s": 2.0**-11, "bf16s": 2.0**-8, "f16r": 2.0**-11, "bf16r": 2.0**-8}
-
-
-def _bf16_round(x32):
-    u = np.ascontiguousarray(x32, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
-    return (u.astype(np.uint32) << 16).view(np.float32)
-
-
-def _to16(x64, storage):
-    x32 = x64.astype(np.float32)
-    if storage.startswith("bf16"):
-        return _bf16_round(x32).astype(np.float64)
-    return x32.astype(np.float16).astype(np.float64)
-
-
-def storage_round(lattice, f, storage, rho0):
-    """The state f (Q, ...) as the encoder stores it, decoded back to float64."""
-    w = LATTICES[lattice].w.reshape((-1,) + (1,) * (f.ndim - 1))
-    if storage in ("f16s", "bf16s"):
-        shift = w * rho0
-    else:
-        acc = f[0].copy()
-        for q in range(1, f.shape[0]):
-            acc = acc + f[q]
-        ref = acc.astype(np.float32).astype(np.float16).astype(np.float64)
-        shift = w * ref[None]
-    return _to16(f - shift, storage) + shift
-
 
 CASES = [
     ("D3Q19", (35, 17, 10), "mrt", False),

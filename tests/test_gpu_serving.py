@@ -65,3 +65,89 @@ def test_serving_refuses_a_request_without_coexistence_and_serves_the_rest():
     assert reqs[1].status == "rejected" and reqs[1].error
     assert reqs[0].status in ("converged", "capped") and reqs[2].status in ("converged", "capped")
     assert out["rejected"] == 1 and out["unfinished"] == 0
+
+
+def test_served_results_match_the_plain_fp64_method():
+    """Continuous batching in float32 against the plain float64 method on the same GPU: each request of a
+    small stream is served (MRT, f32, converged at max|du|/step <= 1e-8 over 100 steps), then solved alone in
+    float64 on the single-lattice path to the same test.  Bar: the droplet's coexistence densities (centre
+    and far field) within 1e-3 relative; the Laplace jump p_EOS(centre) - p_EOS(far field) and the
+    spurious-current maximum are reported beside them."""
+    require_gpu()
+    import plbm_synth as syn
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.serving import Server, from_synth, solve_alone
+
+    fmt("serving_vs_fp64")
+    reqs = from_synth(syn.request_stream(6, 50.0, seed=5, side2d=(48, 96), side3d=(20, 32), t_range=(0.75, 0.9)))
+    srv = Server(budget_bytes=1 << 34, max_slots=8, max_tiles=1 << 16, check_every=100, tol=1e-8,
+                 max_steps=400_000, collision="mrt", record_results=True)
+    out = srv.run(reqs, time_limit=150)
+    srv.close()
+    print({k: v for k, v in out.items() if k != "records"}, flush=True)
+    assert out["unfinished"] == 0 and out["failed"] == 0 and out["rejected"] == 0
+    worst = 0.0
+    for r in reqs:
+        assert r.status == "converged", r.record()
+        st, steps, ref = solve_alone(r, storage="f64", collision="mrt", tol=1e-8, max_steps=400_000)
+        assert st == "converged", (r.record(), st, steps)
+        prm = N.plbm_params_pr_lattice(r.T_over_Tc, 0.326, 2.0, 1.0, 1.0, 1.0)
+
+        def p_eos(x):
+            b = prm.pr_b
+            return x * prm.pr_R * prm.pr_T / (1 - b * x) - prm.pr_a * prm.pr_alpha * x * x / (1 + 2 * b * x - b * b * x * x)
+
+        e_in = abs(r.result["rho_in"] - ref["rho_in"]) / ref["rho_in"]
+        e_out = abs(r.result["rho_out"] - ref["rho_out"]) / ref["rho_out"]
+        dp, dp64 = (p_eos(r.result["rho_in"]) - p_eos(r.result["rho_out"]),
+                    p_eos(ref["rho_in"]) - p_eos(ref["rho_out"]))
+        fmt("serving_vs_fp64_case", id=r.id, lattice=r.lattice, dims=r.dims, T=f"{r.T_over_Tc:.3f}",
+            steps_f32=r.steps, steps_f64=steps, rho_in_err=f"{e_in:.2e}", rho_out_err=f"{e_out:.2e}",
+            laplace_err=f"{abs(dp - dp64) / abs(dp64):.2e}",
+            max_u_err=f"{abs(r.result['max_u'] - ref['max_u']) / ref['max_u']:.2e}")
+        worst = max(worst, e_in, e_out)
+    assert worst <= 1e-3
+
+
+def test_a_request_cancelled_mid_flight_leaves_the_rest_intact():
+    """A running request withdrawn mid-flight is detached and its memory released once its lane's chunk has
+    completed; the other requests are unaffected (bitwise the same as alone)."""
+    require_gpu()
+    import plbm_synth as syn
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+    from paper_2504_15018_amd.serving import Server, from_synth
+
+    fmt("serving_cancel")
+    reqs = from_synth(syn.request_stream(5, 200.0, seed=4, side2d=(32, 64), side3d=(12, 20), t_range=(0.75, 0.9)))
+    victim = max(reqs, key=lambda r: r.nodes)
+    srv = Server(budget_bytes=1 << 34, max_slots=4, max_tiles=4096, check_every=50, tol=1e-7, max_steps=20_000,
+                 keep_lattices=True)
+    state = {"asked": None}
+
+    def watch(_msg):
+        if state["asked"] is None and victim.status == "running" and victim.steps >= 100:
+            state["asked"] = victim.steps
+            srv.cancel(victim.id)
+
+    out = srv.run(reqs, time_limit=120, log=watch)
+    print({k: v for k, v in out.items() if k != "records"}, flush=True)
+    assert state["asked"] is not None
+    assert victim.status == "cancelled" and victim.done is not None
+    # at most one more chunk ran between the request and the release
+    assert victim.steps <= state["asked"] + 50
+    assert out["cancelled"] == 1 and out["unfinished"] == 0
+    assert srv.used == 0 and not srv.resident
+    for r in reqs:
+        if r is victim:
+            continue
+        assert r.status in ("converged", "capped")
+        solo = Lattice(r.lattice, r.dims, r.params, collision="bgk", storage="f32")
+        solo.init_shape(N.PLBM_SHAPE_DROPLET, r.params.rho_l, r.params.rho_v, W=5.0, R=r.radius,
+                        centre=[n / 2.0 for n in r.dims])
+        solo.step(r.steps)
+        assert np.array_equal(solo.populations(), r.lat.populations()), r.record()
+        solo.close()
+        r.lat.close()
+    victim.lat.close()
+    srv.close()
