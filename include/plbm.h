@@ -281,6 +281,17 @@ int plbm_get_time(plbm_lattice* lat, int64_t* t);
  * the NaN or rho <= 0 flag is raised. */
 int plbm_reduce(plbm_lattice* lat, plbm_diag* out);
 
+/* plbm_reduce for callers that cannot allocate device memory or have none to
+ * spare for a workspace.  Same kernels, results and errors as plbm_reduce,
+ * but the per-tile partial records and the final record live in a static
+ * device array inside the library (2 MiB per GPU, held until the process
+ * ends) instead of the lattice's buffer.  Allocates nothing.  The lattice's
+ * device must be current.  Lattices of more than 32 767 tiles are refused
+ * with PLBM_E_NOMEM (plbm_reduce has no such limit).  All calls on one GPU
+ * share the array: calls that overlap in time on one GPU (several streams
+ * or threads) race on it; serialise them. */
+int plbm_reduce_static(plbm_lattice* lat, plbm_diag* out);
+
 /* Release the handle (not the caller's device memory). */
 void plbm_destroy(plbm_lattice* lat);
 

@@ -184,7 +184,8 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
                                                                     const WorkItem* __restrict__ work,
                                                                     int32_t nwork, int32_t phase,
                                                                     double* __restrict__ out_rho,
-                                                                    double* __restrict__ out_u) {
+                                                                    double* __restrict__ out_u,
+                                                                    RedRec* __restrict__ red_out) {
   using T = typename St::T;
   using C = typename St::C;
   constexpr int Q = L::Q, D = L::D, HY = L::HY;
@@ -457,7 +458,7 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
         o.max_du = fmax(o.max_du, q.max_du);
         o.flags = (double)((int)o.flags | (int)q.flags);
       }
-      reinterpret_cast<RedRec*>(kp->red)[tl.tile] = o;
+      (red_out != nullptr ? red_out : reinterpret_cast<RedRec*>(kp->red))[tl.tile] = o;
     }
   }
 }

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -338,7 +339,7 @@ bool graphs_enabled() {
   return on;
 }
 
-int run_step_kernel(plbm_lattice* L, int mode, int phase, double* orho, double* ou) {
+int run_step_kernel(plbm_lattice* L, int mode, int phase, double* orho, double* ou, void* red = nullptr) {
   StepLaunch a{};
   a.lattice = L->desc.lattice;
   a.coll = L->desc.collision;
@@ -354,6 +355,7 @@ int run_step_kernel(plbm_lattice* L, int mode, int phase, double* orho, double* 
   a.phase = phase;
   a.out_rho = orho;
   a.out_u = ou;
+  a.red = red;
   HIPCHK(launch_step(L->desc, a));
   return PLBM_OK;
 }
@@ -693,7 +695,71 @@ int plbm_reduce(plbm_lattice* L, plbm_diag* out) {
   int st = run_step_kernel(L, MODE_REDUCE, (int)(L->t & 1), nullptr, nullptr);
   if (st) return st;
   RedRec* fin = reinterpret_cast<RedRec*>(L->mem + L->lay.red) + L->lay.ntiles;
-  HIPCHK(launch_reduce_final(L->stream, L->kp_dev, L->lay.ntiles, fin));
+  HIPCHK(launch_reduce_final(L->stream, L->kp_dev, L->lay.ntiles, fin, nullptr));
+  RedRec r;
+  HIPCHK(hipMemcpyAsync(&r, fin, sizeof(r), hipMemcpyDeviceToHost, L->stream));
+  HIPCHK(hipStreamSynchronize(L->stream));
+  fill_diag(L, r, out);
+  if (out->flags & (PLBM_FLAG_NAN | PLBM_FLAG_RHO_NONPOS))
+    return set_error(PLBM_E_UNSTABLE, "lattice unstable (flags 0x%x at t = %lld)", out->flags, (long long)L->t);
+  return PLBM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Reductions without a workspace in the lattice's buffer: the tile records
+// and the final record live in a file-scope device array, one per GPU (each
+// device holds its own copy at its own address, kept until the process
+// ends).  Every tile record is written before it is read, so nothing in it
+// needs clearing between calls; calls that overlap on one GPU (two streams)
+// race on it.
+
+namespace {
+
+constexpr int kScratchRecs = 1 << 15;  // 32 768 records of 64 bytes: 2 MiB per GPU
+static __device__ __align__(256) RedRec scratch[kScratchRecs];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // device address of scratch, by device ordinal
+
+// Device address of this device's scratch array (looked up once per device,
+// with that device current).
+int scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(PLBM_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int plbm_reduce_static(plbm_lattice* L, plbm_diag* out) {
+  if (check_lat(L)) return PLBM_E_INVALID;
+  if (!out) return set_error(PLBM_E_INVALID, "null output");
+  const int ntiles = L->lay.ntiles;
+  if (ntiles + 1 > kScratchRecs)
+    return set_error(PLBM_E_NOMEM,
+                     "plbm_reduce_static: the lattice has %d tiles, the static workspace holds %d (use plbm_reduce)",
+                     ntiles, kScratchRecs - 1);
+  void* sp = nullptr;
+  int st = scratch_address(&sp);
+  if (st) return st;
+  st = run_step_kernel(L, MODE_REDUCE, (int)(L->t & 1), nullptr, nullptr, sp);
+  if (st) return st;
+  RedRec* fin = reinterpret_cast<RedRec*>(sp) + ntiles;
+  HIPCHK(launch_reduce_final(L->stream, L->kp_dev, ntiles, fin, sp));
   RedRec r;
   HIPCHK(hipMemcpyAsync(&r, fin, sizeof(r), hipMemcpyDeviceToHost, L->stream));
   HIPCHK(hipStreamSynchronize(L->stream));

@@ -36,8 +36,8 @@ __device__ __forceinline__ void reduce_tiles(const RedRec* __restrict__ r, int n
 }
 
 __global__ __launch_bounds__(256) void k_reduce_final(const KParams* __restrict__ P, int ntiles,
-                                                      RedRec* __restrict__ out) {
-  reduce_tiles(reinterpret_cast<const RedRec*>(P->red), ntiles, out);
+                                                      RedRec* __restrict__ out, const RedRec* __restrict__ recs) {
+  reduce_tiles(recs != nullptr ? recs : reinterpret_cast<const RedRec*>(P->red), ntiles, out);
 }
 
 // One workgroup per batch slot: the same fixed-order combination for every
@@ -49,8 +49,9 @@ __global__ __launch_bounds__(256) void k_reduce_final_batch(const KParams* __res
   reduce_tiles(reinterpret_cast<const RedRec*>(kp->red), kp->ntiles, out + blockIdx.x);
 }
 
-hipError_t launch_reduce_final(hipStream_t st, const KParams* P, int ntiles, void* out) {
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, P, ntiles, reinterpret_cast<RedRec*>(out));
+hipError_t launch_reduce_final(hipStream_t st, const KParams* P, int ntiles, void* out, const void* recs) {
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, P, ntiles, reinterpret_cast<RedRec*>(out),
+                     reinterpret_cast<const RedRec*>(recs));
   return hipGetLastError();
 }
 

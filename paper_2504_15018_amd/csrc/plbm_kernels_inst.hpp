@@ -20,7 +20,8 @@ static hipError_t go_aa(const StepLaunch& a) {
   hipLaunchKernelGGL((k_aa_psi<L, PLBM_ST, TS::TX, TS::TY, WALLS>), dim3((uint32_t)a.nblocks * (uint32_t)a.psplit),
                      dim3(TS::TX * TS::TY), 0, a.stream, a.P, a.work, a.nwork, a.phase, a.psplit);
   hipLaunchKernelGGL((k_aa_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, WALLS>), dim3(a.nblocks),
-                     dim3(TS::TX * TS::TY), 0, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
+                     dim3(TS::TX * TS::TY), 0, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u,
+                     reinterpret_cast<RedRec*>(a.red));
   return hipGetLastError();
 }
 
@@ -30,10 +31,12 @@ static hipError_t go_step(const StepLaunch& a) {
   if (a.aa) return a.walls ? go_aa<L, COLL, MODE, true>(a) : go_aa<L, COLL, MODE, false>(a);
   if (a.walls)
     hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, TS::NT, true>), dim3(a.nblocks), dim3(TS::NT),
-                       PLBM_LDS_PAD, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
+                       PLBM_LDS_PAD, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u,
+                       reinterpret_cast<RedRec*>(a.red));
   else
     hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, TS::NT, false>), dim3(a.nblocks),
-                       dim3(TS::NT), PLBM_LDS_PAD, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u);
+                       dim3(TS::NT), PLBM_LDS_PAD, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u,
+                       reinterpret_cast<RedRec*>(a.red));
   return hipGetLastError();
 }
 

@@ -60,6 +60,7 @@ struct StepLaunch {
   int phase;
   double* out_rho;
   double* out_u;
+  void* red;  // reduce mode: tile records go here instead of the lattice's own (single-lattice launches)
 };
 
 enum : int { AUX_INIT_FIELDS = 0, AUX_INIT_SHAPE = 1, AUX_READ_POP = 2, AUX_WRITE_POP = 3 };
@@ -107,7 +108,8 @@ hipError_t occupancy_step_f16r(int lattice, int coll, int walls, int aa, int* bl
 hipError_t occupancy_step_bf16r(int lattice, int coll, int walls, int aa, int* blocks);
 hipError_t launch_accum(hipStream_t st, int nblocks, int64_t N, int first, const double* in, double* acc);
 hipError_t launch_set_ref(hipStream_t st, int nblocks, const KParams* P, int par, const double* acc);
-hipError_t launch_reduce_final(hipStream_t st, const KParams* P, int ntiles, void* out);
+// recs: the tile records to combine (nullptr: the lattice's own)
+hipError_t launch_reduce_final(hipStream_t st, const KParams* P, int ntiles, void* out, const void* recs);
 hipError_t launch_reduce_final_batch(hipStream_t st, const KParams* P, int nslots, void* out);
 
 }  // namespace plbm

@@ -301,7 +301,8 @@ template <class L, class St, int COLL, int MODE, int TX, int TY, int NT, bool WA
 __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __restrict__ P,
                                                              const WorkItem* __restrict__ work, int32_t nwork,
                                                              int32_t phase, double* __restrict__ out_rho,
-                                                             double* __restrict__ out_u) {
+                                                             double* __restrict__ out_u,
+                                                             RedRec* __restrict__ red_out) {
   using T = typename St::T;
   using C = typename St::C;
   constexpr int Q = L::Q, D = L::D, HY = L::HY;
@@ -828,7 +829,8 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
         o.max_du = fmax(o.max_du, q.max_du);
         o.flags = (double)((int)o.flags | (int)q.flags);
       }
-      reinterpret_cast<RedRec*>(kp->red)[tile] = o;
+      // the lattice's own tile records, or a caller-given record array (single-lattice launches only)
+      (red_out != nullptr ? red_out : reinterpret_cast<RedRec*>(kp->red))[tile] = o;
     }
   }
 }

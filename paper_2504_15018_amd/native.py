@@ -92,6 +92,7 @@ _SIGS = {
     "plbm_write_populations": (ctypes.c_int, [_VP, _DP]),
     "plbm_get_time": (ctypes.c_int, [_VP, ctypes.POINTER(_I64)]),
     "plbm_reduce": (ctypes.c_int, [_VP, ctypes.POINTER(plbm_diag)]),
+    "plbm_reduce_static": (ctypes.c_int, [_VP, ctypes.POINTER(plbm_diag)]),
     "plbm_destroy": (None, [_VP]),
     "plbm_batch_bytes": (ctypes.c_int, [_I32, _I64, ctypes.POINTER(_U64)]),
     "plbm_batch_create": (ctypes.c_int, [_I32, _I64, _VP, _U64, _VP, ctypes.POINTER(_VP)]),
@@ -235,6 +236,14 @@ def plbm_get_time(h):
 def plbm_reduce(h, allow_unstable=False):
     d = plbm_diag()
     code = load().plbm_reduce(h, ctypes.byref(d))
+    if code != PLBM_OK and not (allow_unstable and code == PLBM_E_UNSTABLE):
+        check(code)
+    return d
+
+
+def plbm_reduce_static(h, allow_unstable=False):
+    d = plbm_diag()
+    code = load().plbm_reduce_static(h, ctypes.byref(d))
     if code != PLBM_OK and not (allow_unstable and code == PLBM_E_UNSTABLE):
         check(code)
     return d

@@ -28,7 +28,7 @@ def _declared():
 def test_library_loads_and_exports_every_declared_symbol():
     lib = N.load()
     names = _declared()
-    assert len(names) == len(N.EXPORTED) == 24
+    assert len(names) == len(N.EXPORTED) == 25
     for n in names:
         assert hasattr(lib, n), n
         assert n in N.EXPORTED, n
