@@ -208,11 +208,21 @@ def stream_probe(torch, nodes=256 ** 3, reps=50):
         e1.synchronize()
         return e0.elapsed_time(e1) / 1e3 / reps
 
+    lib.plbm_probe_stream19v.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int,
+                                         ctypes.c_void_p]
+    lib.plbm_probe_copy4u.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
     moved = 2 * 19 * 4 * nodes
-    t19 = timed(lambda: lib.plbm_probe_stream19(a.data_ptr(), b.data_ptr(), nodes, sp))
-    tcp = timed(lambda: lib.plbm_probe_copy4(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp))
-    return {"nodes": nodes, "stream19_blocked_us": round(t19 * 1e6, 1), "stream19_blocked_GBps": round(moved / t19 / 1e9, 1),
-            "copy4_us": round(tcp * 1e6, 1), "copy4_GBps_read_plus_write": round(moved / tcp / 1e9, 1)}
+    out = {"nodes": nodes}
+    runs = [("stream19_blocked", lambda: lib.plbm_probe_stream19(a.data_ptr(), b.data_ptr(), nodes, sp)),
+            ("stream19_blocked_2_per_thread", lambda: lib.plbm_probe_stream19v(a.data_ptr(), b.data_ptr(), nodes, 2, sp)),
+            ("stream19_blocked_4_per_thread", lambda: lib.plbm_probe_stream19v(a.data_ptr(), b.data_ptr(), nodes, 4, sp)),
+            ("copy4", lambda: lib.plbm_probe_copy4(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp)),
+            ("copy4_4_per_thread", lambda: lib.plbm_probe_copy4u(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp))]
+    for name, fn in runs:
+        t = timed(fn)
+        out[name + "_us"] = round(t * 1e6, 1)
+        out[name + "_GBps"] = round(moved / t / 1e9, 1)
+    return out
 
 
 def droplet_precision_run(N, Lattice, lattice, n, R, steps, tr=0.8):

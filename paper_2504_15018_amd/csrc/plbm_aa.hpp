@@ -201,7 +201,7 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
   constexpr bool LOC = St::local;
   __shared__ C lds_psi[4 * PL];                 // 4-plane psi ring
   __shared__ C lds_ref[LOC ? 4 * PL : 1];       // reference densities (locally shifted storage), same ring
-  __shared__ RedRec red_lds[(MODE == MODE_REDUCE) ? NT : 1];
+  __shared__ RedRec red_lds[(MODE == MODE_REDUCE) ? NT / 64 : 1];  // one record per wave
 
   AaTile tl;
   const int wid = work != nullptr ? xcd_remap(blockIdx.x, gridDim.x) : class_remap(blockIdx.x, gridDim.x, P->ntl);
@@ -445,21 +445,7 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
     r.max_u = acc_umax;
     r.max_du = acc_dumax;
     r.flags = (double)acc_flags;
-    red_lds[t] = r;
-    __syncthreads();
-    if (t == 0) {
-      RedRec o = red_lds[0];
-      for (int k = 1; k < NT; ++k) {  // fixed order: deterministic
-        const RedRec& q = red_lds[k];
-        neumaier_add(o.mass_s, o.mass_c, q.mass_s);
-        o.mass_c += q.mass_c;
-        for (int a = 0; a < 3; ++a) o.mom[a] += q.mom[a];
-        o.max_u = fmax(o.max_u, q.max_u);
-        o.max_du = fmax(o.max_du, q.max_du);
-        o.flags = (double)((int)o.flags | (int)q.flags);
-      }
-      (red_out != nullptr ? red_out : reinterpret_cast<RedRec*>(kp->red))[tl.tile] = o;
-    }
+    block_reduce_store<NT>(r, red_lds, (red_out != nullptr ? red_out : reinterpret_cast<RedRec*>(kp->red)) + tl.tile);
   }
 }
 

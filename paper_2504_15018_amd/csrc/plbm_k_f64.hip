@@ -6,33 +6,18 @@
 namespace plbm {
 
 // Combine the per-tile reduction records of one lattice: thread k folds
-// tiles k, k + 256, ... in order, then a fixed pairwise tree in LDS.  The
-// order depends only on the tile count, so the result is deterministic.
-__device__ __forceinline__ void red_combine(RedRec& o, const RedRec& q) {
-  neumaier_add(o.mass_s, o.mass_c, q.mass_s);
-  o.mass_c += q.mass_c;
-  for (int a = 0; a < 3; ++a) o.mom[a] += q.mom[a];
-  o.max_u = fmax(o.max_u, q.max_u);
-  o.max_du = fmax(o.max_du, q.max_du);
-  o.flags = (double)((int)o.flags | (int)q.flags);
-}
-
+// tiles k, k + 256, ... in order, then the workgroup's fixed-order wave
+// reduction.  The order depends only on the tile count, so the result is
+// deterministic.
 __device__ __forceinline__ void reduce_tiles(const RedRec* __restrict__ r, int ntiles, RedRec* __restrict__ out) {
-  __shared__ RedRec sh[256];
-  const int t = threadIdx.x;
+  __shared__ RedRec wl[256 / 64];
   RedRec o;
   o.mass_s = o.mass_c = 0.0;
   o.mom[0] = o.mom[1] = o.mom[2] = 0.0;
   o.max_u = o.max_du = 0.0;
   o.flags = 0.0;
-  for (int k = t; k < ntiles; k += 256) red_combine(o, r[k]);
-  sh[t] = o;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) red_combine(sh[t], sh[t + w]);
-    __syncthreads();
-  }
-  if (t == 0) *out = sh[0];
+  for (int k = threadIdx.x; k < ntiles; k += 256) red_combine(o, r[k]);
+  block_reduce_store<256>(o, wl, out);
 }
 
 __global__ __launch_bounds__(256) void k_reduce_final(const KParams* __restrict__ P, int ntiles,

@@ -58,6 +58,47 @@ __device__ __forceinline__ void neumaier_add(double& s, double& c, double v) {
   s = t;
 }
 
+// Combine two reduction records: compensated mass, summed momentum, maxima,
+// or-ed flags.
+__device__ __forceinline__ void red_combine(RedRec& o, const RedRec& q) {
+  neumaier_add(o.mass_s, o.mass_c, q.mass_s);
+  o.mass_c += q.mass_c;
+  for (int a = 0; a < 3; ++a) o.mom[a] += q.mom[a];
+  o.max_u = fmax(o.max_u, q.max_u);
+  o.max_du = fmax(o.max_du, q.max_du);
+  o.flags = (double)((int)o.flags | (int)q.flags);
+}
+
+// Workgroup reduction of one record per thread, in a fixed order (the result
+// is the same on every run): a butterfly over the 64 lanes of each wave with
+// cross-lane shuffles, then the per-wave results in wave order by one thread,
+// which stores the workgroup's record at *dst.  wl holds NT / 64 records of
+// LDS.  Every thread of the workgroup must call it.
+template <int NT>
+__device__ __forceinline__ void block_reduce_store(RedRec r, RedRec* wl, RedRec* dst) {
+  static_assert(NT % 64 == 0, "whole waves");
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    RedRec q;
+    q.mass_s = __shfl_xor(r.mass_s, off, 64);
+    q.mass_c = __shfl_xor(r.mass_c, off, 64);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q.mom[a] = __shfl_xor(r.mom[a], off, 64);
+    q.max_u = __shfl_xor(r.max_u, off, 64);
+    q.max_du = __shfl_xor(r.max_du, off, 64);
+    q.flags = __shfl_xor(r.flags, off, 64);
+    red_combine(r, q);
+  }
+  const int t = threadIdx.x;
+  if ((t & 63) == 0) wl[t >> 6] = r;
+  __syncthreads();
+  if (t == 0) {
+    RedRec o = wl[0];
+    for (int w = 1; w < NT / 64; ++w) red_combine(o, wl[w]);
+    *dst = o;
+  }
+}
+
 // Map a launch index so that consecutive logical tiles share an XCD (the
 // hardware dispatches workgroups round-robin over the 8 XCDs, each with its
 // own L2); halo re-reads of neighbouring tiles then hit the same L2.
@@ -327,7 +368,7 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
 
   __shared__ C lds_psi[4 * PL + 64];  // 4-plane psi ring + a slot per lane for idle halo lanes
   __shared__ C lds_ref[LOC ? 4 * PL + 64 : 1];  // reference densities, same ring
-  __shared__ RedRec red_lds[(MODE == MODE_REDUCE) ? NT : 1];
+  __shared__ RedRec red_lds[(MODE == MODE_REDUCE) ? NT / 64 : 1];  // one record per wave
 
   int wid = work != nullptr ? xcd_remap(blockIdx.x, gridDim.x) : class_remap(blockIdx.x, gridDim.x, P->ntl);
   int slot = 0, tile = wid;
@@ -816,22 +857,8 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     r.max_u = acc_umax;
     r.max_du = acc_dumax;
     r.flags = (double)acc_flags;
-    red_lds[t] = r;
-    __syncthreads();
-    if (t == 0) {
-      RedRec o = red_lds[0];
-      for (int k = 1; k < NT; ++k) {  // fixed order: deterministic
-        const RedRec& q = red_lds[k];
-        neumaier_add(o.mass_s, o.mass_c, q.mass_s);
-        o.mass_c += q.mass_c;
-        for (int a = 0; a < 3; ++a) o.mom[a] += q.mom[a];
-        o.max_u = fmax(o.max_u, q.max_u);
-        o.max_du = fmax(o.max_du, q.max_du);
-        o.flags = (double)((int)o.flags | (int)q.flags);
-      }
-      // the lattice's own tile records, or a caller-given record array (single-lattice launches only)
-      (red_out != nullptr ? red_out : reinterpret_cast<RedRec*>(kp->red))[tile] = o;
-    }
+    // the lattice's own tile records, or a caller-given record array (single-lattice launches only)
+    block_reduce_store<NT>(r, red_lds, (red_out != nullptr ? red_out : reinterpret_cast<RedRec*>(kp->red)) + tile);
   }
 }
 

@@ -8,7 +8,10 @@
 // stores with the non-temporal hint as in the update kernel.  It moves the
 // update's algorithmic bytes with none of its halo, stencil or collision, so
 // its rate bounds what the update can reach in this layout.
-// k_probe_copy4: a plain float4 copy, one vector per thread.
+// k_probe_stream19v<V>: the same bytes and layout with V = 2 or 4 consecutive
+// nodes per thread (8- or 16-byte accesses per direction).
+// k_probe_copy4: a plain float4 copy, one vector per thread;
+// k_probe_copy4u: the same with four vectors per thread (a block-stride loop).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -29,6 +32,37 @@ __global__ __launch_bounds__(256) void k_probe_stream19(const float* __restrict_
   for (int q = 0; q < kQ; ++q) __builtin_nontemporal_store(v[q] + 1.0f, dst + at + (uint64_t)q * kXB);
 }
 
+template <int V>
+__global__ __launch_bounds__(256) void k_probe_stream19v(const float* __restrict__ src, float* __restrict__ dst,
+                                                         uint32_t nodes) {
+  typedef float vec __attribute__((ext_vector_type(V)));
+  const uint32_t n = (blockIdx.x * 256u + threadIdx.x) * V;  // first of V nodes, in one block of 32
+  if (n >= nodes) return;
+  const uint64_t at = (uint64_t)(n / kXB) * (kQ * kXB) + (n % kXB);
+  vec v[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) v[q] = *reinterpret_cast<const vec*>(src + at + (uint64_t)q * kXB);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q)
+    __builtin_nontemporal_store(v[q] + 1.0f, reinterpret_cast<vec*>(dst + at + (uint64_t)q * kXB));
+}
+
+__global__ __launch_bounds__(256) void k_probe_copy4u(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                      uint64_t n) {
+  const uint64_t base = blockIdx.x * 1024ull + threadIdx.x;
+  float4 v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint64_t i = base + 256ull * k;
+    if (i < n) v[k] = src[i];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint64_t i = base + 256ull * k;
+    if (i < n) dst[i] = v[k];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_probe_copy4(const float4* __restrict__ src, float4* __restrict__ dst,
                                                      uint64_t n) {
   const uint64_t i = blockIdx.x * 256ull + threadIdx.x;
@@ -44,6 +78,30 @@ int plbm_probe_stream19(const void* src, void* dst, uint32_t nodes, void* stream
   if (nodes == 0) return 0;
   hipLaunchKernelGGL(k_probe_stream19, dim3((nodes + 255u) / 256u), dim3(256), 0, (hipStream_t)stream,
                      (const float*)src, (float*)dst, nodes);
+  return (int)hipGetLastError();
+}
+
+// As plbm_probe_stream19 with vec = 2 or 4 nodes per thread; nodes must be a multiple of vec.
+int plbm_probe_stream19v(const void* src, void* dst, uint32_t nodes, int vec, void* stream) {
+  if (nodes == 0) return 0;
+  if ((vec != 2 && vec != 4) || nodes % (uint32_t)vec) return (int)hipErrorInvalidValue;
+  const uint32_t threads = nodes / (uint32_t)vec;
+  if (vec == 2)
+    hipLaunchKernelGGL(k_probe_stream19v<2>, dim3((threads + 255u) / 256u), dim3(256), 0, (hipStream_t)stream,
+                       (const float*)src, (float*)dst, nodes);
+  else
+    hipLaunchKernelGGL(k_probe_stream19v<4>, dim3((threads + 255u) / 256u), dim3(256), 0, (hipStream_t)stream,
+                       (const float*)src, (float*)dst, nodes);
+  return (int)hipGetLastError();
+}
+
+// Four float4 per thread; bytes a multiple of 16 below 2^43.
+int plbm_probe_copy4u(const void* src, void* dst, uint64_t bytes, void* stream) {
+  const uint64_t n = bytes / 16;
+  if (n == 0) return 0;
+  if ((n + 1023) / 1024 > 0x7fffffffull) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_probe_copy4u, dim3((unsigned)((n + 1023) / 1024)), dim3(256), 0, (hipStream_t)stream,
+                     (const float4*)src, (float4*)dst, n);
   return (int)hipGetLastError();
 }
 

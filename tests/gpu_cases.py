@@ -61,6 +61,22 @@ def fmt(name, **kw):
     return s
 
 
+def tols(storage, steps):
+    """Parity bars (relative on f and rho, absolute on u in lattice units) after `steps` steps.
+
+    float64: 1e-12, 1e-12 (the oracle's own rounding is ~1e-16 per operation).
+    float32: 1.5e-6 sqrt(steps) and 2e-7 sqrt(steps).  One update rounds each
+    population through a chain of ~20 float32 operations (2^-24 each), and the
+    roundings of successive steps are independent, so they add in quadrature;
+    measured against the oracle: 1.1e-7 to 2.8e-7 relative on f and 8.8e-8 on
+    u after 3-5 steps of random +-30 % states, 5.8e-6 and 6.0e-7 after 200
+    steps of the 64^3 droplet (the bars leave 3-10x)."""
+    if storage == "f64":
+        return 1e-12, 1e-12
+    r = max(steps, 1) ** 0.5
+    return 1.5e-6 * r, 2e-7 * r
+
+
 def rel_max(a, b):
     return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(np.asarray(b))))
 

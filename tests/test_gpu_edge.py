@@ -2,7 +2,7 @@
 
 * Degenerate shapes against the FP64 oracle: extents of 1 and 2 (a node is its
   own periodic neighbour), a single plane between two walls, lattices smaller
-  than one tile, in both storage patterns; float64 bar 1e-12, float32 2e-6 per
+  than one tile, in both storage patterns; float64 bar 1e-12, float32 gpu_cases.tols per
   step (as the other parity tests).
 * Zero steps change nothing.
 
@@ -14,7 +14,7 @@ import pytest
 
 from oracle import step as S
 
-from gpu_cases import abs_max, fmt, lib_params, oracle_params, rel_max, random_state, require_gpu
+from gpu_cases import abs_max, fmt, lib_params, oracle_params, rel_max, random_state, require_gpu, tols
 
 pytestmark = pytest.mark.gpu
 
@@ -50,7 +50,7 @@ def test_degenerate_shapes_match_the_oracle(case):
     assert np.array_equal(lat.populations(), f0)
     lat.step(steps)
     f_ref = S.run(op, f0, steps)
-    tf, tu = (1e-12, 1e-12) if storage == "f64" else (2e-6 * steps, 1e-6 * steps)
+    tf, tu = tols(storage, steps)
     assert rel_max(lat.populations(), f_ref) <= tf
     rho, u = lat.moments()
     rho_ref, u_ref = S.moments(op, f_ref)
@@ -141,7 +141,7 @@ def test_short_periodic_marching_axis_reads_stay_inside_the_lattice(case, storag
         if storage == "f64":
             tol = 1e-12
         elif storage == "f32":
-            tol = 2e-6 * steps
+            tol = tols(storage, steps)[0]
         else:
             w = LATTICES[lattice].w.reshape((-1,) + (1,) * len(dims))
             dev = np.max(np.abs(ref - w * (rl if shifted else ref.sum(axis=0)[None])))

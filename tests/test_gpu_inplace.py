@@ -2,7 +2,7 @@
 
 * Against the FP64 oracle, on the same bars as the A-B parity tests
   (float64: 1e-12 relative on f and rho, 1e-12 absolute on u; float32:
-  2e-6 / 1e-6 per step), at sizes spanning several tiles with ragged tails,
+  gpu_cases.tols), at sizes spanning several tiles with ragged tails,
   with and without walls, for even and odd step counts.
 * Against the A-B pattern: the two patterns run the same density sum, psi,
   force and collision arithmetic on the same values, so populations, moments
@@ -16,7 +16,7 @@ import pytest
 
 from oracle import step as S
 
-from gpu_cases import abs_max, fmt, lib_params, oracle_params, random_state, rel_max, require_gpu
+from gpu_cases import abs_max, fmt, lib_params, oracle_params, random_state, rel_max, require_gpu, tols
 
 pytestmark = pytest.mark.gpu
 
@@ -51,7 +51,7 @@ def test_inplace_matches_the_oracle(case):
     assert np.array_equal(lat.populations(), f0)  # the canonical read-back of the even-parity layout
     lat.step(steps)
     f_ref = S.run(op, f0, steps)
-    tf, tu = (1e-12, 1e-12) if storage == "f64" else (2e-6 * steps, 1e-6 * steps)
+    tf, tu = tols(storage, steps)
     assert rel_max(lat.populations(), f_ref) <= tf
     rho, u = lat.moments()
     rho_ref, u_ref = S.moments(op, f_ref)

@@ -22,7 +22,7 @@ import pytest
 
 from oracle import step as S
 
-from gpu_cases import abs_max, fmt, lib_params, oracle_params, pr_coex, random_state, rel_max, require_gpu
+from gpu_cases import abs_max, fmt, lib_params, oracle_params, pr_coex, random_state, rel_max, require_gpu, tols
 
 pytestmark = pytest.mark.gpu
 
@@ -59,7 +59,7 @@ def test_wetting_walls_match_the_oracle(case):
         f0 = f0.astype(np.float32).astype(np.float64)
     lat.step(steps)
     f_ref = S.run(op, f0, steps)
-    tf, tu = (1e-12, 1e-12) if storage == "f64" else (2e-6 * steps, 1e-6 * steps)
+    tf, tu = tols(storage, steps)
     assert rel_max(lat.populations(), f_ref) <= tf
     rho, u = lat.moments()
     rho_ref, u_ref = S.moments(op, f_ref)
