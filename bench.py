@@ -31,6 +31,13 @@ array; a psi pass and the in-place update per step).  Its roofline covers the
 two launches of a step together: 3 Q S + 2 C bytes per node (C = 4 bytes,
 the psi value, 8 for float64) over the step's duration.
 
+`--well-balanced` times the well-balanced scheme instead, on the same
+lattice, droplet and storage with the paper's EOS (lattice densities 0.0375 /
+1.187, interface width parameter 3, gradient coefficient 0.15; the lattice
+Peng-Robinson fluid is too stiff for its explicit square-gradient force at
+this interface width): three launches per step (density, chemical potential,
+update), 3 Q S + 4 C algorithmic bytes per node.
+
 `--precision` runs the precision form instead: the 384 x 384 x 128 channel
 in every storage format (coexistence densities and u_x profile against the
 float64 run), then static droplets (D2Q9 512^2, D3Q19 128^3; densities,
@@ -403,6 +410,8 @@ def main():
     ap.add_argument("--pattern", default="ab", choices=["ab", "aa"],
                     help="population storage pattern: two arrays (ab) or in place (aa)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--well-balanced", action="store_true",
+                    help="time the well-balanced scheme (paper EOS fluid, gradient coefficient 0.15)")
     ap.add_argument("--u0", type=float, default=0.0,
                     help="uniform initial velocity along x (0.05: the Galilean-invariance variant of the droplet)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -455,11 +464,16 @@ def main():
         return
     n = args.size
     dims = (n, n, n)
-    prm = N.plbm_params_pr_lattice(0.8, 0.326, 2.0, 1.0, 1.0, 1.0)
+    wb = args.well_balanced
+    if wb:
+        prm = N.plbm_params_paper_lattice(0.0375, 1.187, 3.0, 2.0, 1.0, 1.0, 1.0)
+    else:
+        prm = N.plbm_params_pr_lattice(0.8, 0.326, 2.0, 1.0, 1.0, 1.0)
     log(f"[bench] coexistence rho_v={prm.rho_v:.6f} rho_l={prm.rho_l:.6f}")
-    lat = Lattice("D3Q19", dims, prm, collision=args.collision, storage=args.storage, pattern=args.pattern)
+    lat = Lattice("D3Q19", dims, prm, collision=args.collision, storage=args.storage, pattern=args.pattern,
+                  wb_k=0.15 if wb else 0.0, wb_rho0=0.0375 if wb else 0.0)
     R = 48.0 * n / 256.0
-    lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=5.0, R=R, centre=[n / 2.0] * 3,
+    lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=6.0 if wb else 5.0, R=R, centre=[n / 2.0] * 3,
                    u0=(args.u0, 0.0, 0.0))
     stream = lat.stream
     lat.step(0)  # captures the two-step replay graph now, outside the timed region
@@ -501,7 +515,9 @@ def main():
     # locally shifted storage also reads and writes a 2-byte reference density per node (twice in place: the
     # psi pass writes the new one, the update reads it for the encoder)
     RB = 0 if args.storage in ("f64", "f32", "f16s", "bf16s") else 2
-    if args.pattern == "aa":  # psi pass (Q S read, C written) + in-place update (2 Q S, C of psi read)
+    if wb:  # density pass (Q S, C), chemical-potential pass (C, C), update (2 Q S, C of mu read)
+        bytes_per_launch = (3 * 19 * S + 4 * (8 if args.storage == "f64" else 4)) * nodes
+    elif args.pattern == "aa":  # psi pass (Q S read, C written) + in-place update (2 Q S, C of psi read)
         bytes_per_launch = (3 * 19 * S + 2 * (8 if args.storage == "f64" else 4) + 4 * RB) * nodes
     else:
         bytes_per_launch = (2 * 19 * S + 2 * RB) * nodes
@@ -523,7 +539,7 @@ def main():
         log(f"[bench] serving leg: {serving['converged']} converged, {serving['solves_per_s']} solves/s, "
             f"p50 {serving['latency_p50_s']} s, p99 {serving['latency_p99_s']} s")
     cpu = None if args.no_cpu_baseline else cpu_baseline()
-    tb = profiled_traffic(args.storage, args.collision, n) if args.pattern == "ab" else None
+    tb = profiled_traffic(args.storage, args.collision, n) if (args.pattern == "ab" and not wb) else None
     traffic = None if tb is None else round(tb / 1e9, 4)  # GB per update launch
     out = {
         "metric": "MLUPS & % HBM peak (D3Q19 P-LBM step); solves/s + p99 latency at fixed accuracy",
@@ -540,8 +556,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"D3Q19 static droplet {n}^3 periodic, {args.storage} populations"
                                f"{' (in place)' if args.pattern == 'aa' else ''}, "
-                               f"{args.collision.upper()} + Guo forcing, Peng-Robinson T/Tc=0.8, radius {R:g}, "
-                               f"tanh width 5{f', uniform initial u_x = {args.u0:g}' if args.u0 else ''}; "
+                               + (f"well-balanced scheme (gradient coefficient 0.15), {args.collision.upper()} + Guo "
+                                  f"forcing, paper EOS (0.0375 / 1.187, xi = 3), radius {R:g}, tanh width 6"
+                                  if wb else
+                                  f"{args.collision.upper()} + Guo forcing, Peng-Robinson T/Tc=0.8, radius {R:g}, "
+                                  f"tanh width 5")
+                               + f"{f', uniform initial u_x = {args.u0:g}' if args.u0 else ''}; "
                                f"reduction every {REDUCE_EVERY} steps",
                    "lattice": "D3Q19", "nodes": nodes, "storage": args.storage, "collision": args.collision,
                    "pattern": args.pattern, "lattice_bytes": nbytes,

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define PLBM_ABI_VERSION 3
+#define PLBM_ABI_VERSION 4
 
 /* status codes */
 #define PLBM_OK 0
@@ -91,6 +91,24 @@ extern "C" {
  * storage format (with locally shifted storage the psi pass also writes the
  * nodes' new reference densities). */
 #define PLBM_PATTERN_AA 1
+/* discretisations of the two-phase force */
+#define PLBM_SCHEME_PSEUDOPOTENTIAL 0 /* the paper's update: psi stencil force, eq. (interactionForce) */
+/* Well-balanced discretisation (the class of schemes Sec. VI.B names as the
+ * cure for spurious currents; the paper gives no equations, so this is the
+ * library's reading): the force is written in potential form
+ * F = -rho grad_d mu + F_g with the lattice chemical potential
+ * mu = mu_b(rho) - k lap_d rho (mu_b: the bulk chemical potential of the same
+ * EOS, d mu_b/d rho = p'(rho)/rho; k: gradient coefficient wb_k; grad_d and
+ * lap_d the isotropic lattice stencils), and the equilibrium carries the
+ * constant wb_rho0 on the moving populations at rest
+ * (f_i^eq = w_i wb_rho0 + delta_i0 (rho - wb_rho0) + w_i rho s_i(u)).  A fluid
+ * at rest with uniform mu is then an exact steady state: spurious currents
+ * decay to round-off.  Coexistence follows Maxwell's construction; the
+ * surface tension is int k rho'^2 dx; epsilon and kappa are not used.
+ * Per step: a density pass and a chemical-potential pass (one value per node
+ * each, counted by plbm_lattice_bytes), then the update.  Supported with the
+ * A-B pattern, F64 or F32 storage, mirror walls; not in a batch. */
+#define PLBM_SCHEME_WELL_BALANCED 1
 /* boundary kinds, per axis */
 #define PLBM_PERIODIC 0
 #define PLBM_HALFWAY_BB 1 /* walls half a spacing outside the first and last node */
@@ -166,6 +184,12 @@ typedef struct plbm_lattice_desc {
                           (rho_wall near rho_l wets, near rho_v does not).
                           0 keeps the neutral mirror ghost.  Requires walls;
                           must be finite and >= 0. */
+  int32_t scheme;      /* PLBM_SCHEME_PSEUDOPOTENTIAL (0) | PLBM_SCHEME_WELL_BALANCED */
+  int32_t pad1;
+  double wb_k;         /* well-balanced scheme: gradient coefficient k > 0 */
+  double wb_rho0;      /* well-balanced scheme: reference density of the moving
+                          equilibrium populations; 0 selects rho_v of the
+                          parameters */
 } plbm_lattice_desc;
 
 /* Initial density shape evaluated on the device (tanh interfaces of width W,

@@ -32,6 +32,10 @@ Module map:
   analytic  Appendix A profile, Appendix B surface tension, Young-Laplace,
             channel profile
   norms     error norms (eqs. relative_norms, norms)
+  wellbalanced  the well-balanced discretisation (Sec. VI.B names the class
+            of schemes; the reading is stated in the module): chemical-
+            potential force and an equilibrium with a constant reference
+            density on the moving populations
 
 Readings of passages the paper leaves silent or prints garbled are listed in
 the repository's design notes; the ones that change arithmetic are restated

@@ -67,7 +67,7 @@ struct Layout {
   uint64_t zdata;  // bytes of node data of one z plane of stored populations
   uint64_t zblock; // zdata plus a trash area for the ragged-tile lanes of one workgroup
   int64_t N;
-  uint64_t popA, popB, refA, refB, psi, aux, uprev, red, kp, total;
+  uint64_t popA, popB, refA, refB, psi, aux, uprev, red, kp, wbrho, wbmu, total;
 };
 
 bool local_shift(int storage) { return storage == PLBM_F16R || storage == PLBM_BF16R; }
@@ -159,6 +159,19 @@ int make_layout(const plbm_lattice_desc* d, Layout* L, int64_t resident = 0) {
   if (d->pattern != PLBM_PATTERN_AB && d->pattern != PLBM_PATTERN_AA)
     return set_error(PLBM_E_INVALID, "unknown storage pattern");
   const bool aa = d->pattern == PLBM_PATTERN_AA;
+  if (d->scheme != PLBM_SCHEME_PSEUDOPOTENTIAL && d->scheme != PLBM_SCHEME_WELL_BALANCED)
+    return set_error(PLBM_E_INVALID, "unknown scheme");
+  const bool wb = d->scheme == PLBM_SCHEME_WELL_BALANCED;
+  if (wb) {
+    if (!(d->wb_k > 0.0) || !std::isfinite(d->wb_k)) return set_error(PLBM_E_INVALID, "well-balanced scheme: wb_k > 0");
+    if (!(d->wb_rho0 >= 0.0) || !std::isfinite(d->wb_rho0))
+      return set_error(PLBM_E_INVALID, "well-balanced scheme: wb_rho0 >= 0");
+    if (aa) return set_error(PLBM_E_UNSUPPORTED, "well-balanced scheme: A-B pattern only");
+    if (d->storage != PLBM_F64 && d->storage != PLBM_F32)
+      return set_error(PLBM_E_UNSUPPORTED, "well-balanced scheme: F64 or F32 storage only");
+    if (d->rho_wall[0] > 0.0 || d->rho_wall[1] > 0.0)
+      return set_error(PLBM_E_UNSUPPORTED, "well-balanced scheme: mirror walls only");
+  }
   for (int k = 0; k < 2; ++k) {
     if (!std::isfinite(d->rho_wall[k]) || d->rho_wall[k] < 0.0)
       return set_error(PLBM_E_INVALID, "wall densities must be finite and >= 0");
@@ -236,6 +249,12 @@ int make_layout(const plbm_lattice_desc* d, Layout* L, int64_t resident = 0) {
   off = align_up(off + (uint64_t)(max_tiles + 1) * sizeof(RedRec));
   L->kp = off;
   off = align_up(off + sizeof(KParams));
+  // well-balanced scheme: density and chemical potential of every node (arithmetic type)
+  const uint64_t cb = d->storage == PLBM_F64 ? 8 : 4;
+  L->wbrho = off;
+  if (wb) off = align_up(off + (uint64_t)L->N * cb);
+  L->wbmu = off;
+  if (wb) off = align_up(off + (uint64_t)L->N * cb);
   L->total = off;
   return PLBM_OK;
 }
@@ -320,6 +339,16 @@ int aux_blocks(int64_t N) {
   return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
 }
 
+// Workgroups of the well-balanced passes; in reduce mode each writes one
+// record (never more than the lattice's tile records, which the layout holds).
+int wb_grid(const plbm_lattice* L) {
+  const int b = aux_blocks(L->lay.N);
+  return b < L->lay.ntiles ? b : L->lay.ntiles;
+}
+
+// Records the reduce pass of a lattice writes.
+int reduce_records(const plbm_lattice* L) { return L->kp.wb ? wb_grid(L) : L->lay.ntiles; }
+
 // Workgroups per tile chunk of the in-place pattern's psi pass (measured on
 // 256^3: float32 and float64 fastest with one, 16-bit storage with eight;
 // PLBM_PSI_SPLIT overrides, for tuning; read once).
@@ -356,6 +385,8 @@ int run_step_kernel(plbm_lattice* L, int mode, int phase, double* orho, double* 
   a.out_rho = orho;
   a.out_u = ou;
   a.red = red;
+  a.wb = L->kp.wb;
+  a.wbgrid = a.wb ? wb_grid(L) : 0;
   HIPCHK(launch_step(L->desc, a));
   return PLBM_OK;
 }
@@ -433,6 +464,11 @@ void fill_kparams(plbm_lattice* L) {
   k.nxb = y.nxb;
   k.zblock = (int64_t)y.zblock;
   k.zdata = (int64_t)y.zdata;
+  k.wb = L->desc.scheme == PLBM_SCHEME_WELL_BALANCED;
+  k.wb_k = L->desc.wb_k;
+  k.wb_rho0 = L->desc.wb_rho0 > 0.0 ? L->desc.wb_rho0 : p.rho_v;
+  k.wb_rho = k.wb ? L->mem + y.wbrho : nullptr;
+  k.wb_mu = k.wb ? L->mem + y.wbmu : nullptr;
 }
 
 int check_lat(plbm_lattice* L) { return L ? PLBM_OK : set_error(PLBM_E_INVALID, "null lattice"); }
@@ -695,7 +731,7 @@ int plbm_reduce(plbm_lattice* L, plbm_diag* out) {
   int st = run_step_kernel(L, MODE_REDUCE, (int)(L->t & 1), nullptr, nullptr);
   if (st) return st;
   RedRec* fin = reinterpret_cast<RedRec*>(L->mem + L->lay.red) + L->lay.ntiles;
-  HIPCHK(launch_reduce_final(L->stream, L->kp_dev, L->lay.ntiles, fin, nullptr));
+  HIPCHK(launch_reduce_final(L->stream, L->kp_dev, reduce_records(L), fin, nullptr));
   RedRec r;
   HIPCHK(hipMemcpyAsync(&r, fin, sizeof(r), hipMemcpyDeviceToHost, L->stream));
   HIPCHK(hipStreamSynchronize(L->stream));
@@ -748,7 +784,7 @@ extern "C" {
 int plbm_reduce_static(plbm_lattice* L, plbm_diag* out) {
   if (check_lat(L)) return PLBM_E_INVALID;
   if (!out) return set_error(PLBM_E_INVALID, "null output");
-  const int ntiles = L->lay.ntiles;
+  const int ntiles = reduce_records(L);
   if (ntiles + 1 > kScratchRecs)
     return set_error(PLBM_E_NOMEM,
                      "plbm_reduce_static: the lattice has %d tiles, the static workspace holds %d (use plbm_reduce)",
@@ -931,6 +967,7 @@ int plbm_batch_create(int32_t max_slots, int64_t max_tiles, void* dev_mem, uint6
 
 int plbm_batch_attach(plbm_batch* b, plbm_lattice* L, int32_t* slot) {
   if (!b || !L || !slot) return set_error(PLBM_E_INVALID, "null argument");
+  if (L->kp.wb) return set_error(PLBM_E_UNSUPPORTED, "well-balanced lattices are not batched");
   if (L->batch) return set_error(PLBM_E_INVALID, "lattice already attached to a batch");
   for (int s = 0; s < b->max_slots; ++s) {
     if (!b->lat[s]) {

@@ -69,6 +69,20 @@ __device__ __forceinline__ double shift_density(const KParams& p, int par, int64
   else return p.rho0_shift;
 }
 
+// Equilibrium of the well-balanced scheme, float64: the moving populations
+// carry the constant rho0 at rest, the rest population the remainder.
+template <class L>
+__device__ __forceinline__ double feq64_wb(int i, double rho, const double* u, double rho0) {
+  double cu = 0.0, usq = 0.0;
+#pragma unroll
+  for (int a = 0; a < L::D; ++a) {
+    cu += (double)L::c(i, a) * u[a];
+    usq += u[a] * u[a];
+  }
+  const double base = i == 0 ? rho - (1.0 - L::w[0]) * rho0 : L::w[i] * rho0;
+  return base + L::w[i] * rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+}
+
 template <class L, class St>
 __device__ __forceinline__ void write_equilibrium(const KParams& p, int par, int64_t n, int x, int y, int z,
                                                   double rho, const double* u) {
@@ -78,7 +92,8 @@ __device__ __forceinline__ void write_equilibrium(const KParams& p, int par, int
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     const int dir = storage_dir<L>(p, par, i, z);
-    A[storage_index<L, typename St::T>(p, par, i, x, y, z)] = St::enc64(feq64<L>(i, rho, u), L::w[dir] * rs);
+    const double fe = p.wb ? feq64_wb<L>(i, rho, u, p.wb_rho0) : feq64<L>(i, rho, u);
+    A[storage_index<L, typename St::T>(p, par, i, x, y, z)] = St::enc64(fe, L::w[dir] * rs);
   }
 }
 

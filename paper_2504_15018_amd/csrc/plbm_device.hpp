@@ -248,6 +248,11 @@ struct KParams {
   int32_t nxb;     // x blocks of one 128-byte line per row (storage layout)
   int64_t zblock;  // bytes of one z plane of stored populations (node data + trash)
   int64_t zdata;   // bytes of the node data of one z plane
+  // well-balanced scheme: chemical-potential force and constant-pressure equilibrium
+  int32_t wb;
+  double wb_k, wb_rho0;
+  void* wb_rho;  // density of every node (arithmetic type)
+  void* wb_mu;   // chemical potential of every node (arithmetic type)
 };
 
 // Stored population layout: A[z][y][x / XB][q][x % XB] with XB = 128 bytes /

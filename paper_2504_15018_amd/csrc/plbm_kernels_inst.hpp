@@ -1,8 +1,11 @@
 // Instantiation of every kernel for one storage type.  Included by the
 // per-storage translation units with PLBM_ST (codec) and PLBM_SUFFIX defined.
+#include <type_traits>
+
 #include "plbm_aa.hpp"
 #include "plbm_aux.hpp"
 #include "plbm_launch.hpp"
+#include "plbm_wb.hpp"
 
 #define PLBM_CAT2(a, b) a##b
 #define PLBM_CAT(a, b) PLBM_CAT2(a, b)
@@ -25,9 +28,26 @@ static hipError_t go_aa(const StepLaunch& a) {
   return hipGetLastError();
 }
 
+// Well-balanced scheme (float64 and float32 storage): density pass,
+// chemical-potential pass, update.
+template <class L, int COLL, int MODE>
+static hipError_t go_wb(const StepLaunch& a) {
+  if constexpr (std::is_same<PLBM_ST, StF64>::value || std::is_same<PLBM_ST, StF32>::value) {
+    const dim3 g((uint32_t)a.wbgrid), b(256);
+    hipLaunchKernelGGL((k_wb_rho<L, PLBM_ST>), g, b, 0, a.stream, a.P, a.phase);
+    hipLaunchKernelGGL((k_wb_mu<L, PLBM_ST>), g, b, 0, a.stream, a.P);
+    hipLaunchKernelGGL((k_wb_step<L, PLBM_ST, COLL, MODE>), g, b, 0, a.stream, a.P, a.phase, a.out_rho, a.out_u,
+                       reinterpret_cast<RedRec*>(a.red));
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
 template <class L, int COLL, int MODE>
 static hipError_t go_step(const StepLaunch& a) {
   using TS = TileShape<L>;
+  if (a.wb) return go_wb<L, COLL, MODE>(a);
   if (a.aa) return a.walls ? go_aa<L, COLL, MODE, true>(a) : go_aa<L, COLL, MODE, false>(a);
   if (a.walls)
     hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, TS::NT, true>), dim3(a.nblocks), dim3(TS::NT),

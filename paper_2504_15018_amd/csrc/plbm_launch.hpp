@@ -61,6 +61,8 @@ struct StepLaunch {
   double* out_rho;
   double* out_u;
   void* red;  // reduce mode: tile records go here instead of the lattice's own (single-lattice launches)
+  int wb;      // well-balanced scheme: density, chemical-potential and update passes
+  int wbgrid;  // workgroups of those passes (= reduction records in reduce mode)
 };
 
 enum : int { AUX_INIT_FIELDS = 0, AUX_INIT_SHAPE = 1, AUX_READ_POP = 2, AUX_WRITE_POP = 3 };

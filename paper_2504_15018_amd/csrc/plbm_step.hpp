@@ -244,9 +244,12 @@ __device__ __forceinline__ void stencil_force(const C* s_m, const C* s_0, const 
 // v = f - f_eq + Fhat/2 over the non-hydrodynamic moments of MrtCorr<L>; the
 // moment sums read v_a + v_b (even P_k) or v_a - v_b (odd P_k).
 // dp[p] = f_a - f_b is shared with the momentum sum.
-template <class L, class C, int COLL>
+// WB: the equilibrium of the well-balanced scheme, whose moving populations
+// carry the constant rho0 at rest: f_eq = w rho0 + w rho (-1.5 u.u + 4.5 (c.u)^2)
+// +- O, and f_eq,0 = rho - (1 - w_0) rho0 + w_0 rho (-1.5 u.u).
+template <class L, class C, int COLL, bool WB = false>
 __device__ __forceinline__ void collide(const C* f, const C* dp, C rho, const C* u, const C* F, C omega,
-                                        const C* rate, C* fs) {
+                                        const C* rate, C* fs, C rho0 = (C)0) {
   constexpr int D = L::D;
   using MC = MrtCorr<L>;
   constexpr int K = (COLL == COLL_MRT) ? MC::K : 1;
@@ -260,7 +263,7 @@ __device__ __forceinline__ void collide(const C* f, const C* dp, C rho, const C*
   const C om1 = (C)1 - omega;
   const C omh = (C)1 - (C)0.5 * omega;
   const C w0 = (C)L::w[0];
-  const C E0 = w0 * rho * A;
+  const C E0 = WB ? (rho - (C)(1.0 - L::w[0]) * rho0) + w0 * rho * ((C)-1.5 * usq) : w0 * rho * A;
   const C h0 = -(C)3 * w0 * uF;
   C B0 = omega * E0 + omh * h0;
   C BE[L::P], BO[L::P];
@@ -286,7 +289,7 @@ __device__ __forceinline__ void collide(const C* f, const C* dp, C rho, const C*
       }
     }
     const C w = (C)L::w[ia];
-    const C E = (w * rho) * (A + (C)4.5 * cu * cu);
+    const C E = WB ? w * rho0 + (w * rho) * ((C)-1.5 * usq + (C)4.5 * cu * cu) : (w * rho) * (A + (C)4.5 * cu * cu);
     const C O = ((C)3 * w * rho) * cu;
     const C hE = (C)9 * w * (cu * cF) - (C)3 * w * uF;
     const C hO = ((C)3 * w) * cF;

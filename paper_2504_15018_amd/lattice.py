@@ -17,10 +17,12 @@ Q_OF = {"D2Q9": 9, "D3Q19": 19}
 
 
 def make_desc(lattice, dims, collision="bgk", storage="f64", walls=False, rho0_shift=0.0, mrt_rates=None,
-              pattern="ab", rho_wall=(0.0, 0.0)):
+              pattern="ab", rho_wall=(0.0, 0.0), wb_k=0.0, wb_rho0=0.0):
     """dims = (nx, ny) for D2Q9 or (nx, ny, nz) for D3Q19; walls on the last axis;
     pattern "ab" (two population arrays) or "aa" (in place); rho_wall: wall
-    densities below / above for wetting walls (0: neutral mirror)."""
+    densities below / above for wetting walls (0: neutral mirror); wb_k > 0
+    selects the well-balanced scheme with that gradient coefficient (wb_rho0:
+    its reference density, 0 = rho_v)."""
     d = N.plbm_lattice_desc()
     d.lattice = LATTICE[lattice]
     d.collision = COLLISION[collision]
@@ -34,6 +36,10 @@ def make_desc(lattice, dims, collision="bgk", storage="f64", walls=False, rho0_s
     d.pattern = PATTERN[pattern]
     d.rho_wall[0], d.rho_wall[1] = rho_wall
     d.rho0_shift = rho0_shift
+    if wb_k > 0:
+        d.scheme = N.PLBM_SCHEME_WELL_BALANCED
+        d.wb_k = wb_k
+        d.wb_rho0 = wb_rho0
     for k, v in enumerate(mrt_rates or (0.0, 0.0, 0.0, 0.0)):
         d.mrt_rates[k] = v
     return d
@@ -41,7 +47,8 @@ def make_desc(lattice, dims, collision="bgk", storage="f64", walls=False, rho0_s
 
 class Lattice:
     def __init__(self, lattice, dims, params, collision="bgk", storage="f64", walls=False, rho0_shift=0.0,
-                 mrt_rates=None, stream=None, device="cuda", pattern="ab", rho_wall=(0.0, 0.0)):
+                 mrt_rates=None, stream=None, device="cuda", pattern="ab", rho_wall=(0.0, 0.0), wb_k=0.0,
+                 wb_rho0=0.0):
         import torch
 
         self.name = lattice
@@ -50,7 +57,8 @@ class Lattice:
         self.Q = Q_OF[lattice]
         self.N = int(np.prod(self.dims))
         self.shape = tuple(reversed(self.dims))
-        self.desc = make_desc(lattice, dims, collision, storage, walls, rho0_shift, mrt_rates, pattern, rho_wall)
+        self.desc = make_desc(lattice, dims, collision, storage, walls, rho0_shift, mrt_rates, pattern, rho_wall,
+                              wb_k, wb_rho0)
         self.params = params
         self.nbytes = N.plbm_lattice_bytes(self.desc)
         self.mem = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)

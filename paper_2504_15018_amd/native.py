@@ -13,7 +13,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libplbm.so")
 
 # ---- constants (plbm.h) ----
-PLBM_ABI_VERSION = 3
+PLBM_ABI_VERSION = 4
 PLBM_OK = 0
 PLBM_E_INVALID = -1
 PLBM_E_UNSUPPORTED = -2
@@ -26,6 +26,7 @@ PLBM_BGK, PLBM_MRT = 0, 1
 PLBM_F64, PLBM_F32, PLBM_F16S, PLBM_BF16S, PLBM_F16R, PLBM_BF16R = 0, 1, 2, 3, 4, 5
 PLBM_PERIODIC, PLBM_HALFWAY_BB = 0, 1
 PLBM_PATTERN_AB, PLBM_PATTERN_AA = 0, 1
+PLBM_SCHEME_PSEUDOPOTENTIAL, PLBM_SCHEME_WELL_BALANCED = 0, 1
 PLBM_EOS_PAPER, PLBM_EOS_PENG_ROBINSON = 0, 1
 PLBM_FLAG_NAN, PLBM_FLAG_RHO_NONPOS, PLBM_FLAG_PSI_NEG = 1, 2, 4
 PLBM_SHAPE_SLAB, PLBM_SHAPE_DROPLET, PLBM_SHAPE_LAYERS = 0, 1, 2
@@ -59,7 +60,7 @@ class plbm_lattice_params(ctypes.Structure):
 class plbm_lattice_desc(ctypes.Structure):
     _fields_ = [("lattice", _I32), ("collision", _I32), ("storage", _I32), ("nx", _I32), ("ny", _I32),
                 ("nz", _I32), ("bc", _I32 * 3), ("pattern", _I32), ("rho0_shift", _D), ("mrt_rates", _D * 4),
-                ("rho_wall", _D * 2)]
+                ("rho_wall", _D * 2), ("scheme", _I32), ("pad1", _I32), ("wb_k", _D), ("wb_rho0", _D)]
 
 
 class plbm_shape(ctypes.Structure):

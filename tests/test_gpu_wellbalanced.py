@@ -1,0 +1,178 @@
+"""The well-balanced scheme on the GPU (descriptor scheme = PLBM_SCHEME_WELL_BALANCED).
+
+1. One to four updates of random non-equilibrium states against the oracle's
+   well-balanced update (oracle/wellbalanced.py), D2Q9 and D3Q19, BGK and MRT,
+   periodic and walled, float64 (bar 1e-12) and float32 (gpu_cases.tols);
+   moments and reductions too.
+2. A discrete equilibrium droplet (uniform lattice chemical potential, found on
+   the host by Newton's method from the oracle's equations) is a fixed point on
+   the GPU: 1000 float64 updates leave populations and u = 0 unchanged to
+   round-off.
+3. A static droplet started from a tanh profile: its spurious currents decay
+   to round-off under the well-balanced scheme (float64), while the paper's
+   discretisation of the same fluid keeps them; the settled droplet obeys
+   Young-Laplace with the scheme's planar surface tension.
+The fluid is the paper's EOS (R134a-like lattice densities 0.0375 / 1.187,
+interface width parameter xi = 3), gradient coefficient k = 0.15.
+"""
+import numpy as np
+import pytest
+
+import plbm_synth as syn
+from oracle import eos as E
+from oracle import params as P
+from oracle import step as S
+from oracle import wellbalanced as W
+from oracle.lattice import LATTICES
+
+from gpu_cases import abs_max, fmt, rel_max, require_gpu, tols
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarning")]
+
+RV, RL, XI, K_GRAD = 0.0375, 1.187, 3.0, 0.15
+
+
+def _oracle(lattice, collision, walls, tau_v, tau_l, Fg=(0.0, 0.0, 0.0)):
+    lat = LATTICES[lattice]
+    e = E.PaperEOS(P.K_from_width(XI, RV, RL), RV, RL)
+    cv, cl, _ = P.coexistence(e, 2.0)  # tau(rho) anchors, as the library resolves them
+    bc = tuple("bb" if (walls and a == lat.d - 1) else "periodic" for a in range(lat.d))
+    p = S.StepParams(lat, e, tau_v=tau_v, tau_l=tau_l, rho_v=cv, rho_l=cl, collision=collision, bc=bc,
+                     Fg=tuple(Fg[: lat.d]) + (0.0,) * (3 - lat.d))
+    return W.WBParams(p, K_GRAD, RV)
+
+
+def _lattice(lattice, dims, collision, storage, walls, tau_v, tau_l, Fg=(0.0, 0.0, 0.0)):
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+    prm = N.plbm_params_paper_lattice(RV, RL, XI, 2.0, 1.0, tau_v, tau_l, list(Fg))
+    return Lattice(lattice, dims, prm, collision=collision, storage=storage, walls=walls, wb_k=K_GRAD, wb_rho0=RV)
+
+
+CASES = [
+    # lattice, dims, collision, storage, walls, steps, tau_v, tau_l, Fg
+    ("D2Q9", (37, 29), "bgk", "f64", False, 4, 1.0, 1.0, (0.0, 0.0, 0.0)),
+    ("D2Q9", (40, 33), "mrt", "f64", True, 4, 0.8, 1.1, (1e-5, 0.0, 0.0)),
+    ("D3Q19", (21, 17, 13), "mrt", "f64", False, 3, 0.9, 1.2, (0.0, 0.0, 0.0)),
+    ("D3Q19", (20, 16, 12), "bgk", "f64", True, 3, 1.0, 1.0, (2e-6, -1e-6, 0.0)),
+    ("D3Q19", (35, 17, 10), "mrt", "f32", False, 3, 1.0, 1.0, (0.0, 0.0, 0.0)),
+    ("D2Q9", (70, 37), "bgk", "f32", True, 4, 0.8, 1.1, (0.0, 0.0, 0.0)),
+]
+
+
+def _ids(c):
+    return f"{c[0]}-{'x'.join(map(str, c[1]))}-{c[2]}-{c[3]}-{'bb' if c[4] else 'per'}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_wb_step_matches_the_oracle(case):
+    require_gpu()
+    lattice, dims, collision, storage, walls, steps, tau_v, tau_l, Fg = case
+    fmt("wb_parity", case=_ids(case))
+    wb = _oracle(lattice, collision, walls, tau_v, tau_l, Fg)
+    lat = _lattice(lattice, dims, collision, storage, walls, tau_v, tau_l, Fg)
+    co = syn.grid(dims)
+    rho = syn.droplet(co, dims, RV, RL, R=min(dims) / 3.0, W=2 * XI, centre=[n / 2.0 - 0.3 for n in dims])
+    f0 = syn.random_populations(LATTICES[lattice].Q, co, dims, 11, rho, 0.2)
+    lat.write_populations(f0)
+    if storage == "f32":
+        f0 = f0.astype(np.float32).astype(np.float64)
+    d0 = lat.reduce()
+    lat.step(steps)
+    ref = W.run(wb, f0, steps)
+    tf, tu = tols(storage, steps)
+    f = lat.populations()
+    rho_g, u_g = lat.moments()
+    rho_r, u_r = W.moments(wb, ref)
+    fmt("wb_parity_err", rel_f=f"{rel_max(f, ref):.2e}", rel_rho=f"{rel_max(rho_g, rho_r):.2e}",
+        abs_u=f"{abs_max(u_g, u_r):.2e}")
+    assert rel_max(f, ref) <= tf
+    assert rel_max(rho_g, rho_r) <= tf
+    assert abs_max(u_g, u_r) <= tu
+    d = lat.reduce()
+    assert d.mass == pytest.approx(float(np.sum(rho_r)), rel=1e-12 if storage == "f64" else 1e-6)
+    assert d.max_u == pytest.approx(float(np.max(np.sqrt((u_r ** 2).sum(axis=0)))), rel=1e-9, abs=tu)
+    # mass is conserved by the update
+    assert d.mass == pytest.approx(d0.mass, rel=1e-13 if storage == "f64" else 1e-6)
+    assert d.flags == 0 and d.time == steps
+    lat.close()
+
+
+def _newton_droplet(n, R):
+    from test_oracle_wellbalanced import discrete_equilibrium
+    e = E.PaperEOS(P.K_from_width(XI, RV, RL), RV, RL)
+    co = syn.grid((n, n))
+    return discrete_equilibrium(e, K_GRAD, syn.droplet(co, (n, n), RV, RL, R=R, W=2 * XI))
+
+
+def test_discrete_equilibrium_is_a_fixed_point_on_the_gpu():
+    require_gpu()
+    fmt("wb_fixed_point")
+    n = 128
+    rho = _newton_droplet(n, 32.0)
+    for collision in ("bgk", "mrt"):
+        lat = _lattice("D2Q9", (n, n), collision, "f64", False, 0.8, 1.1)
+        lat.init_fields(rho)
+        f0 = lat.populations()
+        lat.step(1000)
+        f1 = lat.populations()
+        _, u = lat.moments()
+        fmt("wb_fixed_point_err", collision=collision, rel_f=f"{rel_max(f1, f0):.2e}", max_u=f"{np.abs(u).max():.2e}")
+        assert rel_max(f1, f0) <= 1e-13
+        assert np.abs(u).max() <= 1e-14
+        lat.close()
+
+
+def test_spurious_currents_fall_to_round_off_and_laplace_holds():
+    require_gpu()
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("wb_static_droplet")
+    n, R = 128, 32.0
+    e = E.PaperEOS(P.K_from_width(XI, RV, RL), RV, RL)
+    lat = _lattice("D2Q9", (n, n), "bgk", "f64", False, 1.0, 1.0)
+    lat.init_shape(N.PLBM_SHAPE_DROPLET, RL, RV, W=2 * XI, R=R)
+    history = []
+    for _ in range(40):
+        lat.step(50_000)
+        d = lat.reduce()
+        history.append(d.max_u)
+        if d.max_u < 1e-14:
+            break
+    fmt("wb_static_droplet_max_u", history=" ".join(f"{v:.1e}" for v in history))
+    assert history[-1] <= 1e-13
+    rho, u = lat.moments()
+    lat.close()
+    r_in, r_out = rho[n // 2, n // 2], rho[0, 0]
+    R_eq = np.sqrt(np.sum((rho - r_out) / (r_in - r_out)) / np.pi)
+    gamma = W.gamma_planar(e, K_GRAD, RV, RL)
+    dpR = (e.p(r_in) - e.p(r_out)) * R_eq
+    fmt("wb_laplace", R_eq=f"{R_eq:.3f}", dpR_over_gamma=f"{dpR / gamma:.5f}")
+    assert dpR == pytest.approx(gamma, rel=0.01)
+    # the paper's discretisation of the same fluid and droplet keeps spurious currents
+    prm = N.plbm_params_paper_lattice(RV, RL, XI, 2.0, 1.0, 1.0, 1.0, [0.0, 0.0, 0.0])
+    pp = Lattice("D2Q9", (n, n), prm, collision="bgk", storage="f64")
+    pp.init_shape(N.PLBM_SHAPE_DROPLET, RL, RV, W=2 * XI, R=R)
+    pp.step(200_000)
+    d = pp.reduce()
+    fmt("pseudopotential_static_droplet", max_u=f"{d.max_u:.2e}")
+    assert d.max_u > 1e-6
+    pp.close()
+
+
+def test_wb_lattices_are_not_batched():
+    require_gpu()
+    import torch
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("wb_not_batched")
+    prm = N.plbm_params_paper_lattice(RV, RL, XI, 2.0, 1.0, 1.0, 1.0, [0.0, 0.0, 0.0])
+    lat = Lattice("D2Q9", (16, 16), prm, wb_k=K_GRAD)
+    nb = N.plbm_batch_bytes(2, 64)
+    mem = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    b = N.plbm_batch_create(2, 64, (mem.data_ptr() + 255) // 256 * 256, nb, lat.stream.cuda_stream)
+    with pytest.raises(N.PlbmError) as e:
+        N.plbm_batch_attach(b, lat.h)
+    assert e.value.code == N.PLBM_E_UNSUPPORTED
+    N.plbm_batch_destroy(b)
+    lat.close()
