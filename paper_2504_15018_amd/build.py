@@ -86,6 +86,54 @@ def build(jobs=None, verbose=False, out=None, defines=()):
     return lib
 
 
+# Host-side sanitizer build: the host layer (plbm_api.hip, plbm_params.cpp)
+# with AddressSanitizer and UndefinedBehaviorSanitizer on the host pass only
+# (each -fsanitize= follows -Xarch_host; device code is unchanged), linked
+# with the kernel objects of the regular build into _san/libplbm.so.  Load it
+# with PLBM_LIB and the ASan runtime preloaded (sanitizer_runtime()).
+SAN_DIR = os.path.join(PKG, "_san")
+SAN_LIB = os.path.join(SAN_DIR, "libplbm.so")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+HOST_SOURCES = ("plbm_api.hip", "plbm_params.cpp")
+
+
+def sanitizer_runtime():
+    """Path of the compiler's shared ASan runtime (to preload into a non-instrumented host process)."""
+    r = subprocess.run([hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    p = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(p) or not os.path.exists(p):
+        raise RuntimeError("ASan runtime not found")
+    return p
+
+
+def build_sanitized(verbose=False):
+    """Build _san/libplbm.so: sanitized host layer + the regular kernel objects (build() first)."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    kernel_objs = [os.path.join(BUILD, os.path.splitext(s)[0] + ".o") for s in SOURCES if s not in HOST_SOURCES]
+    missing = [o for o in kernel_objs if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError(f"kernel objects missing ({missing[0]}): run build() first")
+    objs = []
+    for src in HOST_SOURCES:
+        obj = os.path.join(SAN_DIR, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc()] + COMMON + SOURCES[src] + SAN_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stderr}")
+        objs.append(obj)
+    tmp = SAN_LIB + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-shared-libsan", "-Xarch_host",
+           "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-o", tmp] + objs + kernel_objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
+    os.replace(tmp, SAN_LIB)
+    if verbose:
+        print(f"built {SAN_LIB}")
+    return SAN_LIB
+
+
 PROBE_SRC = "probe_stream.hip"
 PROBE_LIB = os.path.join(PKG, "libplbm_probe.so")
 
