@@ -502,9 +502,12 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     }
   }
 
-  // logical plane zl -> stored plane in [0, nz).  The march touches
-  // z0 - 1 <= zl <= z1 only, but a periodic axis may be shorter than that
-  // window (nz = 1 or 2), so it wraps as often as needed; walls clamp.
+  // logical plane zl -> stored plane in [0, nz).  The march loads planes
+  // z0 - 1 <= zl <= z1 + 2 (one or two past the last plane the collision
+  // needs, whose values are never used: loading them unconditionally keeps
+  // the unrolled register rotation free of branches), and a periodic axis may
+  // be shorter than that window (nz = 1 or 2), so it wraps as often as
+  // needed; walls clamp.
   auto wrapz = [&](int zl) {
     if constexpr (WALLS) {
       return zl < 0 ? 0 : (zl >= nz ? nz - 1 : zl);
@@ -718,14 +721,12 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     finish(halo_c, z0, true, f0, r0, q0, hb, qh);
     issue(halo_c, z0 + 1, f1, hb, q1, qh);
     finish(halo_c, z0 + 1, true, f1, r1, q1, hb, qh);
-    // loads of z+2 into pf, barrier, collide z, psi of z+2 (planes past z1
-    // are not needed: the last collided plane, z1 - 1, reads psi up to z1)
+    // loads of z+2 into pf, barrier, collide z, psi of z+2
     auto stepz = [&](int z, R* cur, C rc, RefT qc, R* pf, C& rp, RefT& qp) {
-      const bool need = z + 2 <= z1;
-      if (need) issue(halo_c, z + 2, pf, hb, qp, qh);
+      issue(halo_c, z + 2, pf, hb, qp, qh);
       __syncthreads();
       phaseB(z, cur, rc, qc);
-      if (need) finish(halo_c, z + 2, true, pf, rp, qp, hb, qh);
+      finish(halo_c, z + 2, true, pf, rp, qp, hb, qh);
     };
     int z = z0;
     for (; z + 2 < z1; z += 3) {
@@ -754,15 +755,13 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     finish(halo_c, z0, true, fa, ra, qa, ha, qha);
     issue(halo_c, z0 + 1, fb, ha, qb, qha);
     finish(halo_c, z0 + 1, true, fb, rb, qb, ha, qha);
-    if (z0 + 2 <= z1) issue(halo_c, z0 + 2, fc, ha, qc, qha);
-    // planes past z1 are neither loaded nor summed (the last collided plane,
-    // z1 - 1, reads psi up to z1)
+    issue(halo_c, z0 + 2, fc, ha, qc, qha);
     auto stepz = [&](int z, R* cur, C rcur, RefT qcur, R* f2, C& r2, RefT& q2, R* h2, RefT& qh2, R* pf, RefT& qp,
                      R* hp, RefT& qhp) {
-      if (z + 3 <= z1) issue(halo_c, z + 3, pf, hp, qp, qhp);
+      issue(halo_c, z + 3, pf, hp, qp, qhp);
       __syncthreads();
       phaseB(z, cur, rcur, qcur);
-      if (z + 2 <= z1) finish(halo_c, z + 2, true, f2, r2, q2, h2, qh2);
+      finish(halo_c, z + 2, true, f2, r2, q2, h2, qh2);
     };
     int z = z0;
     for (; z + 3 < z1; z += 4) {
@@ -808,29 +807,27 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
       hissue(zl, ha, qa);
       hfinish(zl, ha, qa);
     }
-    // as in the tile march, planes past z1 are neither loaded nor summed
     int z = z0;
 #if PLBM_PREFETCH == 1
     for (; z < z1; ++z) {
-      const bool need = z + 2 <= z1;
-      if (need) hissue(z + 2, ha, qa);
+      hissue(z + 2, ha, qa);
       __syncthreads();
-      if (need) hfinish(z + 2, ha, qa);
+      hfinish(z + 2, ha, qa);
     }
 #else
-    if (z0 + 2 <= z1) hissue(z0 + 2, ha, qa);
+    hissue(z0 + 2, ha, qa);
     for (; z + 1 < z1; z += 2) {
-      if (z + 3 <= z1) hissue(z + 3, hb, qb);
+      hissue(z + 3, hb, qb);
       __syncthreads();
-      if (z + 2 <= z1) hfinish(z + 2, ha, qa);
-      if (z + 4 <= z1) hissue(z + 4, ha, qa);
+      hfinish(z + 2, ha, qa);
+      hissue(z + 4, ha, qa);
       __syncthreads();
-      if (z + 3 <= z1) hfinish(z + 3, hb, qb);
+      hfinish(z + 3, hb, qb);
     }
     if (z < z1) {
-      if (z + 3 <= z1) hissue(z + 3, hb, qb);
+      hissue(z + 3, hb, qb);
       __syncthreads();
-      if (z + 2 <= z1) hfinish(z + 2, ha, qa);
+      hfinish(z + 2, ha, qa);
     }
 #endif
   };

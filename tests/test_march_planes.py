@@ -8,8 +8,9 @@ same order, for both prefetch depths, periodic and walled axes, every axis
 length 1..9 and every chunk length, and checks:
 
 * every stored plane the loads touch (the plane and its two neighbours) lies
-  in [0, nz): a periodic axis shorter than the march's window (nz = 1, 2)
-  must still wrap inside the array;
+  in [0, nz): the march loads one (prefetch 1) or two (prefetch 2) planes past
+  the last one the collision needs, unconditionally, and a periodic axis
+  shorter than that window (nz = 1, 2) must still wrap inside the array;
 * a plane's psi is summed from the register set that was loaded with that
   plane, and a collided plane uses the set holding its own populations;
 * tile waves and halo waves meet the same number of barriers;
@@ -72,13 +73,10 @@ def tile_march(tr, prefetch):
         tr.issue(z0 + 1, "f1"); tr.finish(z0 + 1, "f1", "t")
 
         def stepz(z, cur, pf):
-            need = z + 2 <= z1
-            if need:
-                tr.issue(z + 2, pf)
+            tr.issue(z + 2, pf)
             tr.barrier()
             tr.collide(z, cur)
-            if need:
-                tr.finish(z + 2, pf, "t")
+            tr.finish(z + 2, pf, "t")
 
         z = z0
         while z + 2 < z1:
@@ -93,16 +91,13 @@ def tile_march(tr, prefetch):
         tr.issue(z0 - 1, "fa"); tr.finish(z0 - 1, "fa", "t")
         tr.issue(z0, "fa"); tr.finish(z0, "fa", "t")
         tr.issue(z0 + 1, "fb"); tr.finish(z0 + 1, "fb", "t")
-        if z0 + 2 <= z1:
-            tr.issue(z0 + 2, "fc")
+        tr.issue(z0 + 2, "fc")
 
         def stepz(z, cur, f2, pf):
-            if z + 3 <= z1:
-                tr.issue(z + 3, pf)
+            tr.issue(z + 3, pf)
             tr.barrier()
             tr.collide(z, cur)
-            if z + 2 <= z1:
-                tr.finish(z + 2, f2, "t")
+            tr.finish(z + 2, f2, "t")
 
         z = z0
         while z + 3 < z1:
@@ -126,34 +121,24 @@ def halo_march(tr, prefetch):
     z = z0
     if prefetch == 1:
         while z < z1:
-            need = z + 2 <= z1
-            if need:
-                tr.issue(z + 2, "ha")
+            tr.issue(z + 2, "ha")
             tr.barrier()
-            if need:
-                tr.finish(z + 2, "ha", "h")
+            tr.finish(z + 2, "ha", "h")
             z += 1
     else:
-        if z0 + 2 <= z1:
-            tr.issue(z0 + 2, "ha")
+        tr.issue(z0 + 2, "ha")
         while z + 1 < z1:
-            if z + 3 <= z1:
-                tr.issue(z + 3, "hb")
+            tr.issue(z + 3, "hb")
             tr.barrier()
-            if z + 2 <= z1:
-                tr.finish(z + 2, "ha", "h")
-            if z + 4 <= z1:
-                tr.issue(z + 4, "ha")
+            tr.finish(z + 2, "ha", "h")
+            tr.issue(z + 4, "ha")
             tr.barrier()
-            if z + 3 <= z1:
-                tr.finish(z + 3, "hb", "h")
+            tr.finish(z + 3, "hb", "h")
             z += 2
         if z < z1:
-            if z + 3 <= z1:
-                tr.issue(z + 3, "hb")
+            tr.issue(z + 3, "hb")
             tr.barrier()
-            if z + 2 <= z1:
-                tr.finish(z + 2, "ha", "h")
+            tr.finish(z + 2, "ha", "h")
 
 
 def chunks(nz, cz):
@@ -173,8 +158,8 @@ def test_march_stays_in_bounds_and_race_free(prefetch, walls):
                 assert tt.interval == th.interval == z1 - z0
                 # every collided plane, in order
                 assert sorted({r[2] for r in tt.reads}) == list(range(z0 - 1, z1 + 1))
-                # nothing beyond the last plane the collision reads
-                assert max(tt.loaded) <= z1 and max(th.loaded) <= z1
+                # at most one (prefetch 1) or two (prefetch 2) planes past the last one the collision reads
+                assert max(tt.loaded) <= z1 + prefetch and max(th.loaded) <= z1 + prefetch
                 writes = tt.writes + th.writes
                 for k, slot, zz in tt.reads:
                     # no write to a slot in the interval it is read
@@ -186,8 +171,8 @@ def test_march_stays_in_bounds_and_race_free(prefetch, walls):
 
 
 def test_short_periodic_axis_wraps_inside_the_array():
-    # the window z0 - 1 .. z1 of a chunk, with neighbours, on axes of length 1 and 2
+    # the window z0 - 1 .. z1 + 2 of a chunk, with neighbours, on axes of length 1 and 2
     for nz in (1, 2):
-        for zl in range(-1, nz + 3):
+        for zl in range(-1, nz + 4):
             p = wrapz(zl, nz, False)
             assert 0 <= p < nz and (p - zl) % nz == 0
