@@ -36,13 +36,17 @@ SOURCES = {
     # formats with loads a full plane iteration ahead, the others one phase
     # ahead (the locally shifted ones run 17 % slower a full plane ahead); float64 64 x 4 tiles
     # (seven waves within 256 registers).  Populations are stored with the
-    # non-temporal hint.
+    # non-temporal hint.  The in-place pattern's kernels (no halo waves) use
+    # 64 x 4 tiles in 16-bit storage: three workgroups of four waves per CU
+    # instead of one of eight hide the latency of these instruction-bound
+    # formats (256^3 step 0.787 -> 0.640 ms in f16r, 0.660 -> 0.540 in bf16s;
+    # 64 x 12 and 32 x 4 were slower); float32 stays fastest at 64 x 8.
     "plbm_k_f64.hip": ["-ffp-contract=off", "-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=4"],
     "plbm_k_f32.hip": ["-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3"],
-    "plbm_k_f16s.hip": ["-DPLBM_PREFETCH=2", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3"],
-    "plbm_k_bf16s.hip": ["-DPLBM_PREFETCH=2", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3"],
-    "plbm_k_f16r.hip": ["-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3"],
-    "plbm_k_bf16r.hip": ["-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3"],
+    "plbm_k_f16s.hip": ["-DPLBM_PREFETCH=2", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3", "-DPLBM_AA_TY=4"],
+    "plbm_k_bf16s.hip": ["-DPLBM_PREFETCH=2", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3", "-DPLBM_AA_TY=4"],
+    "plbm_k_f16r.hip": ["-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3", "-DPLBM_AA_TY=4"],
+    "plbm_k_bf16r.hip": ["-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3", "-DPLBM_AA_TY=4"],
     "plbm_api.hip": [],
     "plbm_params.cpp": ["-x", "hip", "-ffp-contract=off"],
 }

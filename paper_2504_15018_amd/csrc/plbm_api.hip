@@ -47,14 +47,14 @@ uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 int storage_bytes(int storage) { return storage == PLBM_F64 ? 8 : storage == PLBM_F32 ? 4 : 2; }
 
-void d3_tile_shape(int storage, int* tx, int* ty) {
+void d3_tile_shape(int storage, int aa, int* tx, int* ty) {
   switch (storage) {
-    case PLBM_F64: return tile_shape_f64(tx, ty);
-    case PLBM_F32: return tile_shape_f32(tx, ty);
-    case PLBM_F16S: return tile_shape_f16s(tx, ty);
-    case PLBM_BF16S: return tile_shape_bf16s(tx, ty);
-    case PLBM_F16R: return tile_shape_f16r(tx, ty);
-    default: return tile_shape_bf16r(tx, ty);
+    case PLBM_F64: return tile_shape_f64(aa, tx, ty);
+    case PLBM_F32: return tile_shape_f32(aa, tx, ty);
+    case PLBM_F16S: return tile_shape_f16s(aa, tx, ty);
+    case PLBM_BF16S: return tile_shape_bf16s(aa, tx, ty);
+    case PLBM_F16R: return tile_shape_f16r(aa, tx, ty);
+    default: return tile_shape_bf16r(aa, tx, ty);
   }
 }
 
@@ -197,7 +197,7 @@ int make_layout(const plbm_lattice_desc* d, Layout* L, int64_t resident = 0) {
     L->tx = TileShape<D2Q9L>::TX;
     L->ty = TileShape<D2Q9L>::TY;
   } else {
-    d3_tile_shape(d->storage, &L->tx, &L->ty);
+    d3_tile_shape(d->storage, aa, &L->tx, &L->ty);
   }
   L->tiles_x = (L->nxk + L->tx - 1) / L->tx;
   L->tiles_y = (L->nyk + L->ty - 1) / L->ty;

@@ -19,7 +19,7 @@ namespace plbm {
 // In-place pattern: the psi pass, then the update.
 template <class L, int COLL, int MODE, bool WALLS>
 static hipError_t go_aa(const StepLaunch& a) {
-  using TS = TileShape<L>;
+  using TS = AaTileShape<L>;
   hipLaunchKernelGGL((k_aa_psi<L, PLBM_ST, TS::TX, TS::TY, WALLS>), dim3((uint32_t)a.nblocks * (uint32_t)a.psplit),
                      dim3(TS::TX * TS::TY), 0, a.stream, a.P, a.work, a.nwork, a.phase, a.psplit);
   hipLaunchKernelGGL((k_aa_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, WALLS>), dim3(a.nblocks),
@@ -74,9 +74,10 @@ hipError_t PLBM_CAT(launch_step_, PLBM_SUFFIX)(const StepLaunch& a) {
 template <class L, int COLL, bool WALLS>
 static hipError_t occ_go(int aa, int* blocks) {
   using TS = TileShape<L>;
+  using AS = AaTileShape<L>;
   if (aa)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        blocks, k_aa_step<L, PLBM_ST, COLL, MODE_STEP, TS::TX, TS::TY, WALLS>, TS::TX * TS::TY, 0);
+        blocks, k_aa_step<L, PLBM_ST, COLL, MODE_STEP, AS::TX, AS::TY, WALLS>, AS::TX * AS::TY, 0);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
       blocks, k_step<L, PLBM_ST, COLL, MODE_STEP, TS::TX, TS::TY, TS::NT, WALLS>, TS::NT, PLBM_LDS_PAD);
 }
@@ -87,9 +88,9 @@ static hipError_t occ_for(int coll, int walls, int aa, int* blocks) {
   return walls ? occ_go<L, COLL_BGK, true>(aa, blocks) : occ_go<L, COLL_BGK, false>(aa, blocks);
 }
 
-void PLBM_CAT(tile_shape_, PLBM_SUFFIX)(int* tx, int* ty) {
-  *tx = TileShape<D3Q19L>::TX;
-  *ty = TileShape<D3Q19L>::TY;
+void PLBM_CAT(tile_shape_, PLBM_SUFFIX)(int aa, int* tx, int* ty) {
+  *tx = aa ? AaTileShape<D3Q19L>::TX : TileShape<D3Q19L>::TX;
+  *ty = aa ? AaTileShape<D3Q19L>::TY : TileShape<D3Q19L>::TY;
 }
 
 hipError_t PLBM_CAT(occupancy_step_, PLBM_SUFFIX)(int lattice, int coll, int walls, int aa, int* blocks) {

@@ -45,6 +45,26 @@ struct TileShape<D2Q9L> {
   static constexpr int NT = TX * TY + (PLBM_HALO_SPLIT ? 64 : 0);
 };
 
+// Tile shape of the in-place pattern's kernels (no halo waves: the psi
+// stencil comes from the psi array), set per storage translation unit; the
+// default is the A-B shape.
+#ifndef PLBM_AA_TX
+#define PLBM_AA_TX PLBM_D3_TX
+#endif
+#ifndef PLBM_AA_TY
+#define PLBM_AA_TY PLBM_D3_TY
+#endif
+template <class L>
+struct AaTileShape;
+template <>
+struct AaTileShape<D3Q19L> {
+  static constexpr int TX = PLBM_AA_TX, TY = PLBM_AA_TY;
+};
+template <>
+struct AaTileShape<D2Q9L> {
+  static constexpr int TX = TileShape<D2Q9L>::TX, TY = 1;
+};
+
 struct StepLaunch {
   int lattice;  // 0 D2Q9, 1 D3Q19
   int coll;     // 0 BGK, 1 MRT
@@ -95,12 +115,13 @@ hipError_t launch_aux_f16r(const AuxLaunch&);
 hipError_t launch_aux_bf16r(const AuxLaunch&);
 // D3Q19 tile shape (x nodes, y rows) of each storage's kernels (compiled per
 // storage translation unit)
-void tile_shape_f64(int* tx, int* ty);
-void tile_shape_f32(int* tx, int* ty);
-void tile_shape_f16s(int* tx, int* ty);
-void tile_shape_bf16s(int* tx, int* ty);
-void tile_shape_f16r(int* tx, int* ty);
-void tile_shape_bf16r(int* tx, int* ty);
+// (aa: the in-place pattern's shape)
+void tile_shape_f64(int aa, int* tx, int* ty);
+void tile_shape_f32(int aa, int* tx, int* ty);
+void tile_shape_f16s(int aa, int* tx, int* ty);
+void tile_shape_bf16s(int aa, int* tx, int* ty);
+void tile_shape_f16r(int aa, int* tx, int* ty);
+void tile_shape_bf16r(int aa, int* tx, int* ty);
 // resident workgroups per CU of the update kernel (hipOccupancy...)
 hipError_t occupancy_step_f64(int lattice, int coll, int walls, int aa, int* blocks);
 hipError_t occupancy_step_f32(int lattice, int coll, int walls, int aa, int* blocks);
