@@ -18,8 +18,8 @@ over its average launch duration measured with HIP events on the lattice's
 stream; `cpu_baseline` times the FP64 NumPy oracle on a bounded sample of the
 same workload on the host (one single-threaded process per core, aggregated).
 
-After the step benchmark, a bounded serving leg runs the serving form at a
-sustainable rate (Poisson arrivals at 0.5 requests/s of the C5 mix for 40 s:
+Before the step benchmark (--serve-first 0: after it), a bounded serving leg
+runs the serving form at a sustainable rate (Poisson arrivals at 0.5 requests/s of the C5 mix for 40 s:
 D2Q9 64^2..1024^2 and D3Q19 64^3..192^3 droplets, T/Tc in [0.6, 0.9], float32
 MRT, converged at max|du|/step <= 1e-8) and reports solves/s and p50/p99
 time to converged solution in the same line, with the accuracy of the
@@ -428,7 +428,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-budget-gb", type=float, default=240.0)
     ap.add_argument("--serve-leg-seconds", type=float, default=40.0,
-                    help="length of the bounded serving leg after the step benchmark (0 skips it)")
+                    help="length of the bounded serving leg (0 skips it)")
+    ap.add_argument("--serve-first", type=int, default=1,
+                    help="1 (default): run the serving leg before the step benchmark; 0: after it")
     ap.add_argument("--serve-collision", default="mrt", choices=["bgk", "mrt"],
                     help="collision of the served lattices (MRT: fewer unstable requests at low T/Tc)")
     args = ap.parse_args()
@@ -462,6 +464,17 @@ def main():
                           **serve_run(N, args.serve_seconds, args.serve_budget_gb, args.serve_collision)}),
               flush=True)
         return
+    serving = None
+
+    def run_serving_leg():
+        out = serving_leg(N, seconds=args.serve_leg_seconds)
+        log(f"[bench] serving leg: {out['converged']} converged, {out['solves_per_s']} solves/s, "
+            f"p50 {out['latency_p50_s']} s, p99 {out['latency_p99_s']} s")
+        torch.cuda.empty_cache()
+        return out
+
+    if args.serve_leg_seconds > 0 and args.serve_first:
+        serving = run_serving_leg()
     n = args.size
     dims = (n, n, n)
     wb = args.well_balanced
@@ -533,11 +546,8 @@ def main():
     lat.close()
     del lat
     torch.cuda.empty_cache()
-    serving = None
-    if args.serve_leg_seconds > 0:
-        serving = serving_leg(N, seconds=args.serve_leg_seconds)
-        log(f"[bench] serving leg: {serving['converged']} converged, {serving['solves_per_s']} solves/s, "
-            f"p50 {serving['latency_p50_s']} s, p99 {serving['latency_p99_s']} s")
+    if args.serve_leg_seconds > 0 and not args.serve_first:
+        serving = run_serving_leg()
     cpu = None if args.no_cpu_baseline else cpu_baseline()
     tb = profiled_traffic(args.storage, args.collision, n) if (args.pattern == "ab" and not wb) else None
     traffic = None if tb is None else round(tb / 1e9, 4)  # GB per update launch
