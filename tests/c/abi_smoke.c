@@ -1,6 +1,7 @@
 /* Plain-C use of libplbm (no Python, no PyTorch): a D3Q19 droplet on a
  * caller-owned hipMalloc buffer and the legacy null stream, 40 steps, checked
- * for the health flags and exact mass conservation (float64 storage), and the
+ * for the health flags and exact mass conservation (float64 storage), the
+ * allocation-free reduction (plbm_reduce_static, equal to plbm_reduce), and the
  * error path of an undersized buffer.  Prints one line; exit status 0 on
  * success. */
 #include <math.h>
@@ -61,7 +62,7 @@ int main(void) {
   s.centre[0] = 20.0;
   s.centre[1] = 16.5;
   s.centre[2] = 13.5;
-  plbm_diag d0, d1;
+  plbm_diag d0, d1, d2;
   if (plbm_init_shape(lat, &s) != PLBM_OK || plbm_reduce(lat, &d0) != PLBM_OK) {
     fprintf(stderr, "init: %s\n", plbm_last_error());
     return 1;
@@ -70,12 +71,19 @@ int main(void) {
     fprintf(stderr, "step: %s\n", plbm_last_error());
     return 1;
   }
+  /* the same reduction from the library's static workspace: identical result */
+  if (plbm_reduce_static(lat, &d2) != PLBM_OK) {
+    fprintf(stderr, "reduce_static: %s\n", plbm_last_error());
+    return 1;
+  }
+  const int same = d2.mass == d1.mass && d2.max_u == d1.max_u && d2.momentum[0] == d1.momentum[0] &&
+                   d2.flags == d1.flags && d2.time == d1.time;
   int64_t t = 0;
   plbm_get_time(lat, &t);
   const double drift = fabs(d1.mass - d0.mass) / d0.mass;
-  printf("c_abi t=%lld mass0=%.15e mass=%.15e drift=%.2e max_u=%.3e flags=%d\n", (long long)t, d0.mass, d1.mass,
-         drift, d1.max_u, d1.flags);
+  printf("c_abi t=%lld mass0=%.15e mass=%.15e drift=%.2e max_u=%.3e flags=%d static_equal=%d\n", (long long)t,
+         d0.mass, d1.mass, drift, d1.max_u, d1.flags, same);
   plbm_destroy(lat);
   hipFree(mem);
-  return (t == 40 && d1.flags == 0 && drift <= 1e-13 && d1.max_u > 0.0) ? 0 : 1;
+  return (t == 40 && d1.flags == 0 && drift <= 1e-13 && d1.max_u > 0.0 && same) ? 0 : 1;
 }

@@ -99,7 +99,7 @@ def test_wb_step_matches_the_oracle(case):
 
 
 def _newton_droplet(n, R):
-    from test_oracle_wellbalanced import discrete_equilibrium
+    from wb_cases import discrete_equilibrium
     e = E.PaperEOS(P.K_from_width(XI, RV, RL), RV, RL)
     co = syn.grid((n, n))
     return discrete_equilibrium(e, K_GRAD, syn.droplet(co, (n, n), RV, RL, R=R, W=2 * XI))
