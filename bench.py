@@ -35,8 +35,10 @@ the psi value, 8 for float64) over the step's duration.
 lattice, droplet and storage with the paper's EOS (lattice densities 0.0375 /
 1.187, interface width parameter 3, gradient coefficient 0.15; the lattice
 Peng-Robinson fluid is too stiff for its explicit square-gradient force at
-this interface width): three launches per step (density, chemical potential,
-update), 3 Q S + 4 C algorithmic bytes per node.
+this interface width): two launches per step (the chemical-potential pass
+reads the populations and writes mu, C bytes per node; the update reads the
+populations and mu and writes the populations), 3 Q S + 2 C algorithmic bytes
+per node over the step's duration.
 
 `--precision` runs the precision form instead: the 384 x 384 x 128 channel
 in every storage format (coexistence densities and u_x profile against the
@@ -528,8 +530,8 @@ def main():
     # locally shifted storage also reads and writes a 2-byte reference density per node (twice in place: the
     # psi pass writes the new one, the update reads it for the encoder)
     RB = 0 if args.storage in ("f64", "f32", "f16s", "bf16s") else 2
-    if wb:  # density pass (Q S, C), chemical-potential pass (C, C), update (2 Q S, C of mu read)
-        bytes_per_launch = (3 * 19 * S + 4 * (8 if args.storage == "f64" else 4)) * nodes
+    if wb:  # chemical-potential pass (Q S read, C written) + update (2 Q S, C of mu read)
+        bytes_per_launch = (3 * 19 * S + 2 * (8 if args.storage == "f64" else 4)) * nodes
     elif args.pattern == "aa":  # psi pass (Q S read, C written) + in-place update (2 Q S, C of psi read)
         bytes_per_launch = (3 * 19 * S + 2 * (8 if args.storage == "f64" else 4) + 4 * RB) * nodes
     else:

@@ -105,9 +105,10 @@ extern "C" {
  * at rest with uniform mu is then an exact steady state: spurious currents
  * decay to round-off.  Coexistence follows Maxwell's construction; the
  * surface tension is int k rho'^2 dx; epsilon and kappa are not used.
- * Per step: a density pass and a chemical-potential pass (one value per node
- * each, counted by plbm_lattice_bytes), then the update.  Supported with the
- * A-B pattern, F64 or F32 storage, mirror walls; not in a batch. */
+ * Per step: a chemical-potential pass (densities of the pulled populations,
+ * mu of every node into one extra value per node, counted by
+ * plbm_lattice_bytes), then the update.  Supported with the A-B pattern, F64
+ * or F32 storage, mirror walls; not in a batch. */
 #define PLBM_SCHEME_WELL_BALANCED 1
 /* boundary kinds, per axis */
 #define PLBM_PERIODIC 0

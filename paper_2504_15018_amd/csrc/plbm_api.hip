@@ -67,7 +67,7 @@ struct Layout {
   uint64_t zdata;  // bytes of node data of one z plane of stored populations
   uint64_t zblock; // zdata plus a trash area for the ragged-tile lanes of one workgroup
   int64_t N;
-  uint64_t popA, popB, refA, refB, psi, aux, uprev, red, kp, wbrho, wbmu, total;
+  uint64_t popA, popB, refA, refB, psi, aux, uprev, red, kp, wbmu, total;
 };
 
 bool local_shift(int storage) { return storage == PLBM_F16R || storage == PLBM_BF16R; }
@@ -249,10 +249,8 @@ int make_layout(const plbm_lattice_desc* d, Layout* L, int64_t resident = 0) {
   off = align_up(off + (uint64_t)(max_tiles + 1) * sizeof(RedRec));
   L->kp = off;
   off = align_up(off + sizeof(KParams));
-  // well-balanced scheme: density and chemical potential of every node (arithmetic type)
+  // well-balanced scheme: chemical potential of every node (arithmetic type)
   const uint64_t cb = d->storage == PLBM_F64 ? 8 : 4;
-  L->wbrho = off;
-  if (wb) off = align_up(off + (uint64_t)L->N * cb);
   L->wbmu = off;
   if (wb) off = align_up(off + (uint64_t)L->N * cb);
   L->total = off;
@@ -339,15 +337,8 @@ int aux_blocks(int64_t N) {
   return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
 }
 
-// Workgroups of the well-balanced passes; in reduce mode each writes one
-// record (never more than the lattice's tile records, which the layout holds).
-int wb_grid(const plbm_lattice* L) {
-  const int b = aux_blocks(L->lay.N);
-  return b < L->lay.ntiles ? b : L->lay.ntiles;
-}
-
-// Records the reduce pass of a lattice writes.
-int reduce_records(const plbm_lattice* L) { return L->kp.wb ? wb_grid(L) : L->lay.ntiles; }
+// Records the reduce pass of a lattice writes (one per tile).
+int reduce_records(const plbm_lattice* L) { return L->lay.ntiles; }
 
 // Workgroups per tile chunk of the in-place pattern's psi pass (measured on
 // 256^3: float32 and float64 fastest with one, 16-bit storage with eight;
@@ -386,7 +377,6 @@ int run_step_kernel(plbm_lattice* L, int mode, int phase, double* orho, double* 
   a.out_u = ou;
   a.red = red;
   a.wb = L->kp.wb;
-  a.wbgrid = a.wb ? wb_grid(L) : 0;
   HIPCHK(launch_step(L->desc, a));
   return PLBM_OK;
 }
@@ -467,7 +457,6 @@ void fill_kparams(plbm_lattice* L) {
   k.wb = L->desc.scheme == PLBM_SCHEME_WELL_BALANCED;
   k.wb_k = L->desc.wb_k;
   k.wb_rho0 = L->desc.wb_rho0 > 0.0 ? L->desc.wb_rho0 : p.rho_v;
-  k.wb_rho = k.wb ? L->mem + y.wbrho : nullptr;
   k.wb_mu = k.wb ? L->mem + y.wbmu : nullptr;
 }
 

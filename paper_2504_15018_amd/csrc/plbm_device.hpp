@@ -251,8 +251,7 @@ struct KParams {
   // well-balanced scheme: chemical-potential force and constant-pressure equilibrium
   int32_t wb;
   double wb_k, wb_rho0;
-  void* wb_rho;  // density of every node (arithmetic type)
-  void* wb_mu;   // chemical potential of every node (arithmetic type)
+  void* wb_mu;  // chemical potential of every node at the current time (arithmetic type)
 };
 
 // Stored population layout: A[z][y][x / XB][q][x % XB] with XB = 128 bytes /
@@ -329,6 +328,24 @@ __device__ __forceinline__ float psi_eval<float>(const EosK& e, double rho, bool
   const double rad = psi_radicand(e, rho);
   *neg = !(rad >= 0.0);
   return sqrtf(rad > 0.0 ? (float)rad : 0.0f);
+}
+
+// Bulk chemical potential per unit mass of the equation of state, float64, up
+// to an additive constant: mu_b = int p / rho^2 d rho + p / rho, so that
+// d mu_b / d rho = p'(rho) / rho (the well-balanced scheme's force).
+__device__ __forceinline__ double mu_bulk(const EosK& e, double rho) {
+  if (e.kind == EOS_PAPER) {
+    // p = K [2 r^3 + c2 r^2 - 3 sv r^2.5 + 2 sv rl r^1.5 + sv rl^2 r^0.5]
+    const double s = sqrt(rho);
+    return e.K * (3.0 * rho * rho + 2.0 * e.c2 * rho - 5.0 * e.sv * rho * s + 6.0 * e.sv * e.rl * s -
+                  e.sv * e.rl2 / s);
+  }
+  // Peng-Robinson: p = r RT / (1 - b r) - aa r^2 / (1 + 2 b r - b^2 r^2)
+  const double r2 = 1.4142135623730951;
+  const double d1 = 1.0 - e.b * rho;
+  const double d2 = 1.0 + 2.0 * e.b * rho - e.b * e.b * rho * rho;
+  return e.RT * log(rho / d1) - e.aa / (2.0 * r2 * e.b) * log((r2 - 1.0 + e.b * rho) / (r2 + 1.0 - e.b * rho)) +
+         e.RT / d1 - e.aa * rho / d2;
 }
 
 // Reciprocal: IEEE division in float64; the hardware reciprocal (1 ulp) in float32.

@@ -5,7 +5,6 @@
 #include "plbm_aa.hpp"
 #include "plbm_aux.hpp"
 #include "plbm_launch.hpp"
-#include "plbm_wb.hpp"
 
 #define PLBM_CAT2(a, b) a##b
 #define PLBM_CAT(a, b) PLBM_CAT2(a, b)
@@ -28,15 +27,17 @@ static hipError_t go_aa(const StepLaunch& a) {
   return hipGetLastError();
 }
 
-// Well-balanced scheme (float64 and float32 storage): density pass,
-// chemical-potential pass, update.
-template <class L, int COLL, int MODE>
+// Well-balanced scheme (float64 and float32 storage): the chemical-potential
+// pass, then the update (or its read-outs), both on the A-B tiling.
+template <class L, int COLL, int MODE, bool WALLS>
 static hipError_t go_wb(const StepLaunch& a) {
   if constexpr (std::is_same<PLBM_ST, StF64>::value || std::is_same<PLBM_ST, StF32>::value) {
-    const dim3 g((uint32_t)a.wbgrid), b(256);
-    hipLaunchKernelGGL((k_wb_rho<L, PLBM_ST>), g, b, 0, a.stream, a.P, a.phase);
-    hipLaunchKernelGGL((k_wb_mu<L, PLBM_ST>), g, b, 0, a.stream, a.P);
-    hipLaunchKernelGGL((k_wb_step<L, PLBM_ST, COLL, MODE>), g, b, 0, a.stream, a.P, a.phase, a.out_rho, a.out_u,
+    using TS = TileShape<L>;
+    hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL_BGK, MODE_MU, TS::TX, TS::TY, TS::NT, WALLS, SCH_WB>),
+                       dim3(a.nblocks), dim3(TS::NT), PLBM_LDS_PAD, a.stream, a.P, a.work, a.nwork, a.phase, nullptr,
+                       nullptr, nullptr);
+    hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, TS::NT, WALLS, SCH_WB>), dim3(a.nblocks),
+                       dim3(TS::NT), PLBM_LDS_PAD, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u,
                        reinterpret_cast<RedRec*>(a.red));
     return hipGetLastError();
   } else {
@@ -47,14 +48,14 @@ static hipError_t go_wb(const StepLaunch& a) {
 template <class L, int COLL, int MODE>
 static hipError_t go_step(const StepLaunch& a) {
   using TS = TileShape<L>;
-  if (a.wb) return go_wb<L, COLL, MODE>(a);
+  if (a.wb) return a.walls ? go_wb<L, COLL, MODE, true>(a) : go_wb<L, COLL, MODE, false>(a);
   if (a.aa) return a.walls ? go_aa<L, COLL, MODE, true>(a) : go_aa<L, COLL, MODE, false>(a);
   if (a.walls)
-    hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, TS::NT, true>), dim3(a.nblocks), dim3(TS::NT),
+    hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, TS::NT, true, SCH_PP>), dim3(a.nblocks), dim3(TS::NT),
                        PLBM_LDS_PAD, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u,
                        reinterpret_cast<RedRec*>(a.red));
   else
-    hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, TS::NT, false>), dim3(a.nblocks),
+    hipLaunchKernelGGL((k_step<L, PLBM_ST, COLL, MODE, TS::TX, TS::TY, TS::NT, false, SCH_PP>), dim3(a.nblocks),
                        dim3(TS::NT), PLBM_LDS_PAD, a.stream, a.P, a.work, a.nwork, a.phase, a.out_rho, a.out_u,
                        reinterpret_cast<RedRec*>(a.red));
   return hipGetLastError();
@@ -79,7 +80,7 @@ static hipError_t occ_go(int aa, int* blocks) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
         blocks, k_aa_step<L, PLBM_ST, COLL, MODE_STEP, AS::TX, AS::TY, WALLS>, AS::TX * AS::TY, 0);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks, k_step<L, PLBM_ST, COLL, MODE_STEP, TS::TX, TS::TY, TS::NT, WALLS>, TS::NT, PLBM_LDS_PAD);
+      blocks, k_step<L, PLBM_ST, COLL, MODE_STEP, TS::TX, TS::TY, TS::NT, WALLS, SCH_PP>, TS::NT, PLBM_LDS_PAD);
 }
 
 template <class L>

@@ -81,8 +81,7 @@ struct StepLaunch {
   double* out_rho;
   double* out_u;
   void* red;  // reduce mode: tile records go here instead of the lattice's own (single-lattice launches)
-  int wb;      // well-balanced scheme: density, chemical-potential and update passes
-  int wbgrid;  // workgroups of those passes (= reduction records in reduce mode)
+  int wb;     // well-balanced scheme: chemical-potential pass, then the update
 };
 
 enum : int { AUX_INIT_FIELDS = 0, AUX_INIT_SHAPE = 1, AUX_READ_POP = 2, AUX_WRITE_POP = 3 };

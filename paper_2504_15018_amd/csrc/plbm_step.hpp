@@ -12,9 +12,25 @@
 //      the Q post-collision populations with coalesced writes.
 // HBM traffic is the algorithmic 2 Q S bytes per node; the halo ring and the
 // two extra planes per chunk are re-read from L2 / the Infinity Cache.
+//
+// The same march carries the well-balanced scheme (SCH_WB), whose force is
+// F = -rho grad_d mu + F_g with the chemical potential
+// mu = mu_b(rho) - k lap_d rho (mu_b: float64 bulk chemical potential of the
+// EOS), lap_d g = 6 sum_i w_i (g(x + c_i) - g(x)), grad_d g = 3 sum_i w_i c_i
+// g(x + c_i), and whose equilibrium carries a constant reference density rho0
+// on the moving populations at rest.  mu needs rho one node out and the force
+// needs mu one node out, so a step is two launches:
+//   MODE_MU  the LDS ring holds rho of the pulled populations (tile and halo);
+//            phase B evaluates mu of the plane and stores it per node;
+//   update   the ring holds mu loaded from that array (the halo waves load one
+//            value per node instead of pulling Q populations); phase B forms
+//            the force and collides with the well-balanced equilibrium.
+// Beyond a half-way bounce-back wall rho and mu mirror the wall-adjacent
+// plane (the clamped plane index).
 #pragma once
 
 #include <type_traits>
+#include <utility>
 
 #include "plbm_device.hpp"
 
@@ -29,12 +45,16 @@ namespace plbm {
 #ifndef PLBM_MIN_WAVES
 #define PLBM_MIN_WAVES 2  // waves per SIMD the register allocation must allow
 #endif
+#ifndef PLBM_MU_PREFETCH
+#define PLBM_MU_PREFETCH 3  // plane loads in flight per wave in the chemical-potential pass
+#endif
 #ifndef PLBM_HALO_PRIO
 #define PLBM_HALO_PRIO 1  // wave issue priority of the halo waves (0: that of the tile waves)
 #endif
 
 enum : int { COLL_BGK = 0, COLL_MRT = 1 };
-enum : int { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_REDUCE = 2 };
+enum : int { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_REDUCE = 2, MODE_MU = 3 };
+enum : int { SCH_PP = 0, SCH_WB = 1 };  // pseudopotential force / well-balanced scheme
 
 struct WorkItem {
   int32_t slot;
@@ -235,6 +255,45 @@ __device__ __forceinline__ void stencil_force(const C* s_m, const C* s_0, const 
   }
 }
 
+// Value of a 3-plane LDS ring (planes z-1, z, z+1; rows of W2) at x + c_i.
+template <class L, class C, int W2>
+__device__ __forceinline__ C ring_at(const C* s_m, const C* s_0, const C* s_p, int il, int i) {
+  const int cz = L::cz[i];
+  return (cz > 0 ? s_p : (cz < 0 ? s_m : s_0))[il + L::cy[i] * W2 + L::cx[i]];
+}
+
+// Well-balanced scheme: chemical potential of a node from the density ring,
+// mu = mu_b(rho) - k 6 sum_i w_i (rho(x + c_i) - rho(x)), in float64.
+template <class L, class C, int W2>
+__device__ __forceinline__ double wb_mu_node(const EosK& eos, const C* s_m, const C* s_0, const C* s_p, int il,
+                                             double k) {
+  const double r0 = (double)s_0[il];
+  double lap = 0.0;
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) lap += L::w[i] * ((double)ring_at<L, C, W2>(s_m, s_0, s_p, il, i) - r0);
+  return mu_bulk(eos, r0) - k * 6.0 * lap;
+}
+
+// Well-balanced scheme: F = -rho grad_d mu + F_g from the chemical-potential
+// ring, grad_d mu = 3 sum_i w_i c_i mu(x + c_i).
+template <class L, class C, int W2>
+__device__ __forceinline__ void wb_force(const C* s_m, const C* s_0, const C* s_p, int il, C rho, const C* Fg,
+                                         C* F) {
+  constexpr int D = L::D;
+  C g[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) g[a] = 0;
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    const C mi = ring_at<L, C, W2>(s_m, s_0, s_p, il, i);
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      if (L::c(i, a) != 0) g[a] += (C)(3.0 * L::w[i] * L::c(i, a)) * mi;
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) F[a] = -rho * g[a] + Fg[a];
+}
+
 // BGK collision with Guo forcing (eqs. LBE, Single_Phase_EDF,
 // Guo_Forcing_Scheme), dt = 1:  f* = (1 - omega) f + omega f_eq + (1 - omega/2) Fhat,
 // written per opposite pair (a, b = opp a) through even and odd parts:
@@ -340,8 +399,21 @@ template <bool B>
 struct BoolC {
   static constexpr bool value = B;
 };
+template <int K>
+struct IntC {
+  static constexpr int value = K;
+};
+// f(IntC<0>{}), ..., f(IntC<N-1>{}), in order
+template <int N, class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(IntC<I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
 
-template <class L, class St, int COLL, int MODE, int TX, int TY, int NT, bool WALLS>
+template <class L, class St, int COLL, int MODE, int TX, int TY, int NT, bool WALLS, int SCH>
 __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __restrict__ P,
                                                              const WorkItem* __restrict__ work, int32_t nwork,
                                                              int32_t phase, double* __restrict__ out_rho,
@@ -368,6 +440,19 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   constexpr bool RAW = St::shifted;
   constexpr bool LOC = St::local;  // per-node reference densities
   using R = typename std::conditional<RAW, T, C>::type;
+  // well-balanced scheme: the chemical-potential pass (ring: rho) or the
+  // update and its read-outs (ring: mu)
+  constexpr bool WB = SCH == SCH_WB;
+  constexpr bool WBMU = WB && MODE == MODE_MU;
+  constexpr bool WBLD = WB && MODE != MODE_MU;
+  static_assert(!WB || (!RAW && !LOC), "well-balanced scheme: float64 or float32 storage");
+  static_assert(WB || MODE != MODE_MU, "MODE_MU belongs to the well-balanced scheme");
+  // per-node value carried with a plane's populations through the march: the
+  // reference density (locally shifted storage) or the chemical potential
+  // (well-balanced update)
+  using QT = typename std::conditional<WBLD, C, RefT>::type;
+  // plane iterations between issuing a plane's loads and summing it
+  constexpr int PF = PLBM_PREFETCH;
 
   __shared__ C lds_psi[4 * PL + 64];  // 4-plane psi ring + a slot per lane for idle halo lanes
   __shared__ C lds_ref[LOC ? 4 * PL + 64 : 1];  // reference densities, same ring
@@ -555,6 +640,9 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   const void* const ref_src = LOC ? kp->ref[par] : nullptr;
   void* const ref_dst = LOC ? kp->ref[par ^ 1] : nullptr;
   auto ref_ld = [&](uint32_t n) -> RefT { return gld_at<RefT>(ref_src, n); };
+  // well-balanced scheme: the per-node chemical potential (read by the update, written by MODE_MU)
+  void* const mu_arr = WB ? kp->wb_mu : nullptr;
+  auto mu_ld = [&](uint32_t n) -> C { return gld_at<C>(mu_arr, n); };
 
   bool psi_neg = false;
 
@@ -562,7 +650,7 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   // previous plane is collided: issue() pulls the populations of logical
   // plane zl (tile node into fo, halo node into ho); finish() sums rho and
   // writes psi of the tile and the halo ring into the LDS ring.
-  auto issue = [&](auto halo_c, int zl, R* fo, R* ho, RefT& qo, RefT& qh) {
+  auto issue = [&](auto halo_c, int zl, R* fo, R* ho, QT& qo, QT& qh) {
     constexpr bool HALO = decltype(halo_c)::value;
     const int pz = wrapz(zl);
     const int zm = pz == 0 ? (WALLS ? 0 : nz - 1) : pz - 1;
@@ -573,21 +661,31 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     const bool lo = WALLS && pz == 0;
     const bool hi = WALLS && pz == nz - 1;
     pull(ioxy, bm, b0, bp, lo, hi, fo);
-    if constexpr (HALO) pull(hoxy, bm, b0, bp, lo, hi, ho);
+    if constexpr (WBLD) {
+      qo = mu_ld((uint32_t)(pz * plane + own));
+      if constexpr (HALO) qh = mu_ld((uint32_t)(pz * plane + hown));
+    } else if constexpr (HALO) {
+      pull(hoxy, bm, b0, bp, lo, hi, ho);
+    }
     if constexpr (LOC) {
       qo = ref_ld((uint32_t)(pz * plane + own));
       if constexpr (HALO) qh = ref_ld((uint32_t)(pz * plane + hown));
     }
   };
-  auto as_ref = [&](RefT v) -> C {
+  auto as_ref = [&](QT v) -> C {
     if constexpr (LOC) return (C)v;
     else return (C)0;
   };
-  auto finish = [&](auto halo_c, int zl, bool keep, const R* fo, C& ro, RefT qo, const R* ho, RefT qh) {
+  auto finish = [&](auto halo_c, int zl, bool keep, const R* fo, C& ro, QT qo, const R* ho, QT qh) {
     constexpr bool HALO = decltype(halo_c)::value;
     C* sl = lds_psi + ((zl - z0 + 1) & 3) * PL;
     const C r = density(fo, as_ref(qo));
     ro = r;
+    if constexpr (WB) {
+      sl[ilds] = WBLD ? (C)qo : r;
+      if constexpr (HALO) (hlds < 4 * PL ? sl : lds_psi)[hlds] = WBLD ? (C)qh : density(ho, as_ref(qh));
+      return;
+    }
     bool ng;
     sl[ilds] = ghost_psi(zl, psi_eval<C>(eos, (double)r, &ng));
     psi_neg |= ng && ivalid && keep;
@@ -622,7 +720,16 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   int acc_flags = 0;
 
   // Phase B for output plane z with the populations f / rho of that plane.
-  auto phaseB = [&](int z, const R* fr, C rho, RefT qr) {
+  const C wb_rho0 = WB ? (C)kp->wb_rho0 : (C)0;
+  const double wb_k = WB ? kp->wb_k : 0.0;
+  auto phaseB = [&](int z, const R* fr, C rho, QT qr) {
+    if constexpr (WBMU) {
+      if (ivalid)
+        gst_at<C>(mu_arr, (uint32_t)(z * plane + own),
+                  (C)wb_mu_node<L, C, W2>(eos, lds_psi + ((z - z0) & 3) * PL, lds_psi + ((z - z0 + 1) & 3) * PL,
+                                          lds_psi + ((z - z0 + 2) & 3) * PL, ilds, wb_k));
+      return;
+    }
     C f[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = decode(fr, i, as_ref(qr));
@@ -630,7 +737,10 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     const C* s_0 = lds_psi + ((z - z0 + 1) & 3) * PL;
     const C* s_p = lds_psi + ((z - z0 + 2) & 3) * PL;
     C F[D], u[D];
-    stencil_force<L, C, W2>(s_m, s_0, s_p, ilds, cA, cB, cC, Fg, F);
+    if constexpr (WB)
+      wb_force<L, C, W2>(s_m, s_0, s_p, ilds, rho, Fg, F);
+    else
+      stencil_force<L, C, W2>(s_m, s_0, s_p, ilds, cA, cB, cC, Fg, F);
     // j_a = sum_i f_i c_ia over opposite pairs
     C dp[L::P];
 #pragma unroll
@@ -650,7 +760,7 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     if (MODE == MODE_STEP) {
       const C omega = recip(tau_v + (rho - rho_v) * tau_slope);
       C fs[Q];
-      collide<L, C, COLL>(f, dp, rho, u, F, omega, rate, fs);
+      collide<L, C, COLL, WB>(f, dp, rho, u, F, omega, rate, fs, wb_rho0);
       char* dz = dst + (uint64_t)z * zblock;
       if constexpr (LOC) {
         // f*_i(x) is decoded next step by x + c_i (by x itself when it
@@ -710,11 +820,10 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   // population register sets rotate roles (unrolled by three, no copies):
   // plane z is collided while plane z+1 waits with its psi in LDS and the
   // loads of plane z+2 are in flight.
-#if PLBM_PREFETCH == 1
-  auto march = [&](auto halo_c) {
+  auto march1 = [&](auto halo_c) {
     R f0[Q], f1[Q], f2[Q], hb[Q];
     C r0, r1, r2;      // densities
-    RefT q0 = 0, q1 = 0, q2 = 0, qh = 0;  // reference densities (LOC)
+    QT q0 = 0, q1 = 0, q2 = 0, qh = 0;  // reference densities (LOC) or mu (well-balanced update)
     issue(halo_c, z0 - 1, f0, hb, q0, qh);
     finish(halo_c, z0 - 1, false, f0, r0, q0, hb, qh);
     issue(halo_c, z0, f0, hb, q0, qh);
@@ -722,7 +831,7 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     issue(halo_c, z0 + 1, f1, hb, q1, qh);
     finish(halo_c, z0 + 1, true, f1, r1, q1, hb, qh);
     // loads of z+2 into pf, barrier, collide z, psi of z+2
-    auto stepz = [&](int z, R* cur, C rc, RefT qc, R* pf, C& rp, RefT& qp) {
+    auto stepz = [&](int z, R* cur, C rc, QT qc, R* pf, C& rp, QT& qp) {
       issue(halo_c, z + 2, pf, hb, qp, qh);
       __syncthreads();
       phaseB(z, cur, rc, qc);
@@ -740,15 +849,14 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     }
     if (z < z1) stepz(z, f1, r1, q1, f0, r0, q0);
   };
-#else
   // Loads run a full plane iteration ahead of their use: iteration z issues
   // plane z+3, collides plane z and sums the density and psi of plane z+2,
   // whose loads were issued one iteration earlier.  Four population register
   // sets and two halo sets rotate (unrolled by four, no copies).
-  auto march = [&](auto halo_c) {
+  auto march2 = [&](auto halo_c) {
     R fa[Q], fb[Q], fc[Q], fd[Q], ha[Q], hb[Q];
     C ra, rb, rc, rd;
-    RefT qa = 0, qb = 0, qc = 0, qd = 0, qha = 0, qhb = 0;  // reference densities (LOC)
+    QT qa = 0, qb = 0, qc = 0, qd = 0, qha = 0, qhb = 0;  // reference densities (LOC) or mu
     issue(halo_c, z0 - 1, fa, ha, qa, qha);
     finish(halo_c, z0 - 1, false, fa, ra, qa, ha, qha);
     issue(halo_c, z0, fa, ha, qa, qha);
@@ -756,8 +864,8 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     issue(halo_c, z0 + 1, fb, ha, qb, qha);
     finish(halo_c, z0 + 1, true, fb, rb, qb, ha, qha);
     issue(halo_c, z0 + 2, fc, ha, qc, qha);
-    auto stepz = [&](int z, R* cur, C rcur, RefT qcur, R* f2, C& r2, RefT& q2, R* h2, RefT& qh2, R* pf, RefT& qp,
-                     R* hp, RefT& qhp) {
+    auto stepz = [&](int z, R* cur, C rcur, QT qcur, R* f2, C& r2, QT& q2, R* h2, QT& qh2, R* pf, QT& qp,
+                     R* hp, QT& qhp) {
       issue(halo_c, z + 3, pf, hp, qp, qhp);
       __syncthreads();
       phaseB(z, cur, rcur, qcur);
@@ -780,23 +888,68 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     }
     if (z < z1) stepz(z, fc, rc, qc, fa, ra, qa, ha, qha, fb, qb, hb, qhb);
   };
-#endif
+  auto march = [&](auto halo_c) {
+    if constexpr (PF == 1)
+      march1(halo_c);
+    else
+      march2(halo_c);
+  };
+  // The chemical-potential pass has no collision to hide a plane's loads
+  // behind, and needs a plane's populations only to sum its density, so it
+  // keeps NM planes of loads in flight in NM register sets: iteration z issues
+  // plane z+1+NM, evaluates mu of plane z and sums plane z+2 (issued NM-1
+  // iterations earlier).  Plane z0+2+j uses set j mod NM; the loop is unrolled
+  // by NM so that every set index is a constant.
+  constexpr int NM = PLBM_MU_PREFETCH;
+  static_assert(NM >= 1, "at least one plane in flight");
+  auto march_mu = [&](auto halo_c) {
+    R fs[NM][Q], hs[NM][Q];
+    QT qs[NM] = {}, qhs[NM] = {};
+    C rd;
+    for (int zl = z0 - 1; zl <= z0 + 1; ++zl) {
+      issue(halo_c, zl, fs[0], hs[0], qs[0], qhs[0]);
+      finish(halo_c, zl, true, fs[0], rd, qs[0], hs[0], qhs[0]);
+    }
+#pragma unroll
+    for (int j = 0; j + 1 < NM; ++j) issue(halo_c, z0 + 2 + j, fs[j], hs[j], qs[j], qhs[j]);
+    auto stepmu = [&](int z, auto u_c) {
+      constexpr int u = decltype(u_c)::value, ui = (u + NM - 1) % NM;
+      issue(halo_c, z + 1 + NM, fs[ui], hs[ui], qs[ui], qhs[ui]);
+      __syncthreads();
+      phaseB(z, fs[u], rd, qs[u]);
+      finish(halo_c, z + 2, true, fs[u], rd, qs[u], hs[u], qhs[u]);
+    };
+    int z = z0;
+    for (; z + NM - 1 < z1; z += NM)
+      static_for<NM>([&](auto u_c) { stepmu(z + decltype(u_c)::value, u_c); });
+    static_for<NM - 1>([&](auto u_c) {
+      if (z + decltype(u_c)::value < z1) stepmu(z + decltype(u_c)::value, u_c);
+    });
+  };
   // Halo waves (SPLIT): pull the ring nodes of a plane, sum their density and
   // write their psi, with the same barriers as the tile waves and the same
   // distance between issuing a plane's loads and summing it.
   auto march_halo = [&]() {
     R ha[Q], hb[Q];
-    RefT qa = 0, qb = 0;
-    auto hissue = [&](int zl, R* ho, RefT& qh) {
+    QT qa = 0, qb = 0;
+    auto hissue = [&](int zl, R* ho, QT& qh) {
       const int pz = wrapz(zl);
+      if constexpr (WBLD) {
+        qh = mu_ld((uint32_t)(pz * plane + hown));
+        return;
+      }
       const int zm = pz == 0 ? (WALLS ? 0 : nz - 1) : pz - 1;
       const int zp = pz == nz - 1 ? (WALLS ? nz - 1 : 0) : pz + 1;
       pull(hoxy, src + (uint64_t)zm * zblock, src + (uint64_t)pz * zblock, src + (uint64_t)zp * zblock,
            WALLS && pz == 0, WALLS && pz == nz - 1, ho);
       if constexpr (LOC) qh = ref_ld((uint32_t)(pz * plane + hown));
     };
-    auto hfinish = [&](int zl, const R* ho, RefT qh) {
+    auto hfinish = [&](int zl, const R* ho, QT qh) {
       const int slot = ((zl - z0 + 1) & 3) * PL;
+      if constexpr (WB) {
+        (hlds < 4 * PL ? lds_psi + slot : lds_psi)[hlds] = WBLD ? (C)qh : density(ho, as_ref(qh));
+        return;
+      }
       const C rh = density(ho, as_ref(qh));
       bool hng;
       const C ph = ghost_psi(zl, psi_eval<C>(eos, (double)rh, &hng));
@@ -808,30 +961,75 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
       hfinish(zl, ha, qa);
     }
     int z = z0;
-#if PLBM_PREFETCH == 1
-    for (; z < z1; ++z) {
-      hissue(z + 2, ha, qa);
-      __syncthreads();
-      hfinish(z + 2, ha, qa);
+    if constexpr (PF == 1) {
+      for (; z < z1; ++z) {
+        hissue(z + 2, ha, qa);
+        __syncthreads();
+        hfinish(z + 2, ha, qa);
+      }
+    } else {
+      hissue(z0 + 2, ha, qa);
+      for (; z + 1 < z1; z += 2) {
+        hissue(z + 3, hb, qb);
+        __syncthreads();
+        hfinish(z + 2, ha, qa);
+        hissue(z + 4, ha, qa);
+        __syncthreads();
+        hfinish(z + 3, hb, qb);
+      }
+      if (z < z1) {
+        hissue(z + 3, hb, qb);
+        __syncthreads();
+        hfinish(z + 2, ha, qa);
+      }
     }
-#else
-    hissue(z0 + 2, ha, qa);
-    for (; z + 1 < z1; z += 2) {
-      hissue(z + 3, hb, qb);
-      __syncthreads();
-      hfinish(z + 2, ha, qa);
-      hissue(z + 4, ha, qa);
-      __syncthreads();
-      hfinish(z + 3, hb, qb);
-    }
-    if (z < z1) {
-      hissue(z + 3, hb, qb);
-      __syncthreads();
-      hfinish(z + 2, ha, qa);
-    }
-#endif
   };
-  if constexpr (SPLIT) {
+  auto march_halo_mu = [&]() {
+    R hs[NM][Q];
+    QT qhs[NM] = {};
+    auto hissue = [&](int zl, R* ho) {
+      const int pz = wrapz(zl);
+      const int zm = pz == 0 ? (WALLS ? 0 : nz - 1) : pz - 1;
+      const int zp = pz == nz - 1 ? (WALLS ? nz - 1 : 0) : pz + 1;
+      pull(hoxy, src + (uint64_t)zm * zblock, src + (uint64_t)pz * zblock, src + (uint64_t)zp * zblock,
+           WALLS && pz == 0, WALLS && pz == nz - 1, ho);
+    };
+    auto hfinish = [&](int zl, const R* ho, QT qh) {
+      (hlds < 4 * PL ? lds_psi + ((zl - z0 + 1) & 3) * PL : lds_psi)[hlds] = density(ho, as_ref(qh));
+    };
+    for (int zl = z0 - 1; zl <= z0 + 1; ++zl) {
+      hissue(zl, hs[0]);
+      hfinish(zl, hs[0], qhs[0]);
+    }
+#pragma unroll
+    for (int j = 0; j + 1 < NM; ++j) hissue(z0 + 2 + j, hs[j]);
+    auto hstep = [&](int z, auto u_c) {
+      constexpr int u = decltype(u_c)::value, ui = (u + NM - 1) % NM;
+      hissue(z + 1 + NM, hs[ui]);
+      __syncthreads();
+      hfinish(z + 2, hs[u], qhs[u]);
+    };
+    int z = z0;
+    for (; z + NM - 1 < z1; z += NM)
+      static_for<NM>([&](auto u_c) { hstep(z + decltype(u_c)::value, u_c); });
+    static_for<NM - 1>([&](auto u_c) {
+      if (z + decltype(u_c)::value < z1) hstep(z + decltype(u_c)::value, u_c);
+    });
+  };
+  if constexpr (WBMU) {
+    if constexpr (SPLIT) {
+      if (PLBM_HALO_PRIO > 0 && halo_thread) __builtin_amdgcn_s_setprio(PLBM_HALO_PRIO);
+      if (halo_thread)
+        march_halo_mu();
+      else
+        march_mu(BoolC<false>{});
+    } else {
+      if (wave < HW)
+        march_mu(BoolC<true>{});
+      else
+        march_mu(BoolC<false>{});
+    }
+  } else if constexpr (SPLIT) {
     // Every tile wave waits at the plane barrier for the psi ring the halo
     // waves produce; issue priority for the halo waves shortens that wait.
     if (PLBM_HALO_PRIO > 0 && halo_thread) __builtin_amdgcn_s_setprio(PLBM_HALO_PRIO);
