@@ -220,11 +220,19 @@ def stream_probe(torch, nodes=256 ** 3, reps=50):
     lib.plbm_probe_stream19v.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int,
                                          ctypes.c_void_p]
     lib.plbm_probe_copy4u.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+    lib.plbm_probe_stream19x.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_void_p]
     moved = 2 * 19 * 4 * nodes
     out = {"nodes": nodes}
     runs = [("stream19_blocked", lambda: lib.plbm_probe_stream19(a.data_ptr(), b.data_ptr(), nodes, sp)),
             ("stream19_blocked_2_per_thread", lambda: lib.plbm_probe_stream19v(a.data_ptr(), b.data_ptr(), nodes, 2, sp)),
             ("stream19_blocked_4_per_thread", lambda: lib.plbm_probe_stream19v(a.data_ptr(), b.data_ptr(), nodes, 4, sp)),
+            ("stream19_blocks_of_64", lambda: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, 64, 1, sp)),
+            ("stream19_blocks_of_64_2_per_thread",
+             lambda: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, 64, 2, sp)),
+            ("stream19_blocks_of_128", lambda: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, 128, 1, sp)),
+            ("stream19_blocks_of_128_2_per_thread",
+             lambda: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, 128, 2, sp)),
             ("copy4", lambda: lib.plbm_probe_copy4(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp)),
             ("copy4_4_per_thread", lambda: lib.plbm_probe_copy4u(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp))]
     for name, fn in runs:

@@ -10,6 +10,8 @@
 // its rate bounds what the update can reach in this layout.
 // k_probe_stream19v<V>: the same bytes and layout with V = 2 or 4 consecutive
 // nodes per thread (8- or 16-byte accesses per direction).
+// k_probe_stream19x<XB, V>: the same bytes in blocks of XB = 32, 64 or 128
+// nodes (128, 256 or 512 bytes per direction), V = 1 or 2 nodes per thread.
 // k_probe_copy4: a plain float4 copy, one vector per thread;
 // k_probe_copy4u: the same with four vectors per thread (a block-stride loop).
 #include <hip/hip_runtime.h>
@@ -45,6 +47,21 @@ __global__ __launch_bounds__(256) void k_probe_stream19v(const float* __restrict
 #pragma unroll
   for (int q = 0; q < kQ; ++q)
     __builtin_nontemporal_store(v[q] + 1.0f, reinterpret_cast<vec*>(dst + at + (uint64_t)q * kXB));
+}
+
+template <int XB, int V>
+__global__ __launch_bounds__(256) void k_probe_stream19x(const float* __restrict__ src, float* __restrict__ dst,
+                                                         uint32_t nodes) {
+  typedef float vec __attribute__((ext_vector_type(V)));
+  const uint32_t n = (blockIdx.x * 256u + threadIdx.x) * V;
+  if (n >= nodes) return;
+  const uint64_t at = (uint64_t)(n / XB) * (kQ * XB) + (n % XB);
+  vec v[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) v[q] = *reinterpret_cast<const vec*>(src + at + (uint64_t)q * XB);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q)
+    __builtin_nontemporal_store(v[q] + 1.0f, reinterpret_cast<vec*>(dst + at + (uint64_t)q * XB));
 }
 
 __global__ __launch_bounds__(256) void k_probe_copy4u(const float4* __restrict__ src, float4* __restrict__ dst,
@@ -92,6 +109,25 @@ int plbm_probe_stream19v(const void* src, void* dst, uint32_t nodes, int vec, vo
   else
     hipLaunchKernelGGL(k_probe_stream19v<4>, dim3((threads + 255u) / 256u), dim3(256), 0, (hipStream_t)stream,
                        (const float*)src, (float*)dst, nodes);
+  return (int)hipGetLastError();
+}
+
+// Blocks of xb = 32, 64 or 128 nodes, vec = 1 or 2 nodes per thread; nodes a
+// multiple of xb; src and dst hold 19 * nodes floats each.
+int plbm_probe_stream19x(const void* src, void* dst, uint32_t nodes, int xb, int vec, void* stream) {
+  if (nodes == 0) return 0;
+  if ((xb != 32 && xb != 64 && xb != 128) || (vec != 1 && vec != 2) || nodes % (uint32_t)xb)
+    return (int)hipErrorInvalidValue;
+  const dim3 g((nodes / (uint32_t)vec + 255u) / 256u), b(256);
+  const hipStream_t st = (hipStream_t)stream;
+  const float* s = (const float*)src;
+  float* d = (float*)dst;
+  if (xb == 32 && vec == 1) hipLaunchKernelGGL((k_probe_stream19x<32, 1>), g, b, 0, st, s, d, nodes);
+  if (xb == 32 && vec == 2) hipLaunchKernelGGL((k_probe_stream19x<32, 2>), g, b, 0, st, s, d, nodes);
+  if (xb == 64 && vec == 1) hipLaunchKernelGGL((k_probe_stream19x<64, 1>), g, b, 0, st, s, d, nodes);
+  if (xb == 64 && vec == 2) hipLaunchKernelGGL((k_probe_stream19x<64, 2>), g, b, 0, st, s, d, nodes);
+  if (xb == 128 && vec == 1) hipLaunchKernelGGL((k_probe_stream19x<128, 1>), g, b, 0, st, s, d, nodes);
+  if (xb == 128 && vec == 2) hipLaunchKernelGGL((k_probe_stream19x<128, 2>), g, b, 0, st, s, d, nodes);
   return (int)hipGetLastError();
 }
 
