@@ -248,10 +248,17 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
     const int hx = ((x0 + jx) % nx + nx) % nx, hy = ((y0 + jy) % ny + ny) % ny;  // periodic in x and y
     po[k] = (uint32_t)(hy * nx + hx);
   }
+  // ring planes zl in [z0 - 1, z1 + 1]; a periodic axis may be shorter than
+  // that window (nz = 1), so it wraps as often as needed; walls clamp (the
+  // mirror psi ghost)
   auto wrapz = [&](int zl) {
-    if (zl < 0) return WALLS ? 0 : zl + nz;  // mirror psi ghost at a wall
-    if (zl >= nz) return WALLS ? nz - 1 : zl - nz;
-    return zl;
+    if constexpr (WALLS) {
+      return zl < 0 ? 0 : (zl >= nz ? nz - 1 : zl);
+    } else {
+      while (zl < 0) zl += nz;
+      while (zl >= nz) zl -= nz;
+      return zl;
+    }
   };
   // wetting walls: psi(rho_w) on the ghost plane instead of the mirror
   const bool wet_lo = WALLS && kp->rho_wall[0] > 0.0, wet_hi = WALLS && kp->rho_wall[1] > 0.0;
@@ -270,19 +277,32 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
   // written by the psi pass (ref_dst) and staged into LDS with psi
   const void* const ref_src = LOC ? kp->ref[par] : nullptr;
   const void* const ref_dst = LOC ? kp->ref[par ^ 1] : nullptr;
-  auto stage_psi = [&](int zl) {
+  // psi (and reference densities) of ring plane zl: loaded into registers a
+  // plane iteration before they are written to the LDS ring, so that the
+  // loads are in flight across a whole update
+  auto psi_issue = [&](int zl, C* pv, RefT* rv) {
     const uint32_t pz = (uint32_t)wrapz(zl) * plane;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      if (pact[k]) pv[k] = gld_at<C>(psi, pz + po[k]);
+    if constexpr (LOC) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        if (pact[k]) rv[k] = gld_at<RefT>(ref_dst, pz + po[k]);
+    }
+  };
+  auto psi_commit = [&](int zl, const C* pv, const RefT* rv) {
     C* sl = lds_psi + ((zl - z0 + 1) & 3) * PL;
     const bool ghost = WALLS && ((zl < 0 && wet_lo) || (zl >= nz && wet_hi));
     const C gv = zl < 0 ? psw_lo : psw_hi;
 #pragma unroll
     for (int k = 0; k < 2; ++k)
-      if (pact[k]) sl[t + k * NT] = ghost ? gv : gld_at<C>(psi, pz + po[k]);
+      if (pact[k]) sl[t + k * NT] = ghost ? gv : pv[k];
     if constexpr (LOC) {
       C* rl = lds_ref + ((zl - z0 + 1) & 3) * PL;
 #pragma unroll
       for (int k = 0; k < 2; ++k)
-        if (pact[k]) rl[t + k * NT] = (C)gld_at<RefT>(ref_dst, pz + po[k]);
+        if (pact[k]) rl[t + k * NT] = (C)rv[k];
     }
   };
   auto load = [&](int z, T* v) {
@@ -414,26 +434,35 @@ __global__ __launch_bounds__(TX* TY, PLBM_MIN_WAVES) void k_aa_step(const KParam
     }
   };
 
-  // One barrier per plane: plane z + 1 of psi is staged into the slot last
-  // read two planes ago, while the populations of plane z + 1 are already in
-  // flight (a node's slots are disjoint from every other node's, so reading
-  // them before plane z is written back is safe).
+  // One barrier per plane: psi of plane z + 1 (loaded during the previous
+  // plane) goes into the slot last read two planes ago, the psi loads of plane
+  // z + 2 and the populations of plane z + 1 are issued (a node's slots are
+  // disjoint from every other node's, so reading them before plane z is
+  // written back is safe), then plane z is updated.  Two register sets of
+  // each rotate (unrolled by two).  The psi loads of plane z1 + 1 after the
+  // last plane are never used.
   T va[Q], vb[Q];
-  stage_psi(z0 - 1);
-  stage_psi(z0);
+  C pa[2] = {}, pb[2] = {};
+  RefT ra[2] = {}, rb[2] = {};
+  psi_issue(z0 - 1, pa, ra);
+  psi_commit(z0 - 1, pa, ra);
+  psi_issue(z0, pa, ra);
+  psi_commit(z0, pa, ra);
+  psi_issue(z0 + 1, pa, ra);
   load(z0, va);
-  auto plane_step = [&](int z, const T* cur, T* nxt) {
-    stage_psi(z + 1);
+  auto plane_step = [&](int z, const T* cur, T* nxt, const C* pc, const RefT* rc, C* pn, RefT* rn) {
+    psi_commit(z + 1, pc, rc);
+    psi_issue(z + 2, pn, rn);
     if (z + 1 < z1) load(z + 1, nxt);
     __syncthreads();
     update(z, cur);
   };
   int z = z0;
   for (; z + 1 < z1; z += 2) {
-    plane_step(z, va, vb);
-    plane_step(z + 1, vb, va);
+    plane_step(z, va, vb, pa, ra, pb, rb);
+    plane_step(z + 1, vb, va, pb, rb, pa, ra);
   }
-  if (z < z1) plane_step(z, va, vb);
+  if (z < z1) plane_step(z, va, vb, pa, ra, pb, rb);
 
   if (MODE == MODE_REDUCE) {
     RedRec r;
