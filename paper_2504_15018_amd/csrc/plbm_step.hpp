@@ -48,6 +48,9 @@ namespace plbm {
 #ifndef PLBM_MU_PREFETCH
 #define PLBM_MU_PREFETCH 3  // plane loads in flight per wave in the chemical-potential pass
 #endif
+#ifndef PLBM_HALO_PREFETCH
+#define PLBM_HALO_PREFETCH PLBM_PREFETCH  // plane loads in flight per halo wave
+#endif
 #ifndef PLBM_HALO_PRIO
 #define PLBM_HALO_PRIO 1  // wave issue priority of the halo waves (0: that of the tile waves)
 #endif
@@ -927,11 +930,17 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     });
   };
   // Halo waves (SPLIT): pull the ring nodes of a plane, sum their density and
-  // write their psi, with the same barriers as the tile waves and the same
-  // distance between issuing a plane's loads and summing it.
+  // write their psi (or, in the well-balanced scheme, their density or the
+  // loaded mu), with the same barriers as the tile waves.  They keep NH planes
+  // of loads in flight in NH register sets (plane z0+2+j in set j mod NH,
+  // unrolled by NH): iteration z issues plane z+1+NH and writes plane z+2.
+  // The ring a plane barrier waits for is the halo waves' work, so their loads
+  // may run further ahead than the tile waves'.
+  constexpr int NH = WBMU ? NM : PLBM_HALO_PREFETCH;
+  static_assert(NH >= 1, "at least one plane in flight");
   auto march_halo = [&]() {
-    R ha[Q], hb[Q];
-    QT qa = 0, qb = 0;
+    R hs[NH][Q];
+    QT qhs[NH] = {};
     auto hissue = [&](int zl, R* ho, QT& qh) {
       const int pz = wrapz(zl);
       if constexpr (WBLD) {
@@ -957,62 +966,21 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
       if constexpr (LOC) (hlds < 4 * PL ? lds_ref + slot : lds_ref)[hlds] = (C)(RefT)rh;
     };
     for (int zl = z0 - 1; zl <= z0 + 1; ++zl) {
-      hissue(zl, ha, qa);
-      hfinish(zl, ha, qa);
-    }
-    int z = z0;
-    if constexpr (PF == 1) {
-      for (; z < z1; ++z) {
-        hissue(z + 2, ha, qa);
-        __syncthreads();
-        hfinish(z + 2, ha, qa);
-      }
-    } else {
-      hissue(z0 + 2, ha, qa);
-      for (; z + 1 < z1; z += 2) {
-        hissue(z + 3, hb, qb);
-        __syncthreads();
-        hfinish(z + 2, ha, qa);
-        hissue(z + 4, ha, qa);
-        __syncthreads();
-        hfinish(z + 3, hb, qb);
-      }
-      if (z < z1) {
-        hissue(z + 3, hb, qb);
-        __syncthreads();
-        hfinish(z + 2, ha, qa);
-      }
-    }
-  };
-  auto march_halo_mu = [&]() {
-    R hs[NM][Q];
-    QT qhs[NM] = {};
-    auto hissue = [&](int zl, R* ho) {
-      const int pz = wrapz(zl);
-      const int zm = pz == 0 ? (WALLS ? 0 : nz - 1) : pz - 1;
-      const int zp = pz == nz - 1 ? (WALLS ? nz - 1 : 0) : pz + 1;
-      pull(hoxy, src + (uint64_t)zm * zblock, src + (uint64_t)pz * zblock, src + (uint64_t)zp * zblock,
-           WALLS && pz == 0, WALLS && pz == nz - 1, ho);
-    };
-    auto hfinish = [&](int zl, const R* ho, QT qh) {
-      (hlds < 4 * PL ? lds_psi + ((zl - z0 + 1) & 3) * PL : lds_psi)[hlds] = density(ho, as_ref(qh));
-    };
-    for (int zl = z0 - 1; zl <= z0 + 1; ++zl) {
-      hissue(zl, hs[0]);
+      hissue(zl, hs[0], qhs[0]);
       hfinish(zl, hs[0], qhs[0]);
     }
 #pragma unroll
-    for (int j = 0; j + 1 < NM; ++j) hissue(z0 + 2 + j, hs[j]);
+    for (int j = 0; j + 1 < NH; ++j) hissue(z0 + 2 + j, hs[j], qhs[j]);
     auto hstep = [&](int z, auto u_c) {
-      constexpr int u = decltype(u_c)::value, ui = (u + NM - 1) % NM;
-      hissue(z + 1 + NM, hs[ui]);
+      constexpr int u = decltype(u_c)::value, ui = (u + NH - 1) % NH;
+      hissue(z + 1 + NH, hs[ui], qhs[ui]);
       __syncthreads();
       hfinish(z + 2, hs[u], qhs[u]);
     };
     int z = z0;
-    for (; z + NM - 1 < z1; z += NM)
-      static_for<NM>([&](auto u_c) { hstep(z + decltype(u_c)::value, u_c); });
-    static_for<NM - 1>([&](auto u_c) {
+    for (; z + NH - 1 < z1; z += NH)
+      static_for<NH>([&](auto u_c) { hstep(z + decltype(u_c)::value, u_c); });
+    static_for<NH - 1>([&](auto u_c) {
       if (z + decltype(u_c)::value < z1) hstep(z + decltype(u_c)::value, u_c);
     });
   };
@@ -1020,7 +988,7 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
     if constexpr (SPLIT) {
       if (PLBM_HALO_PRIO > 0 && halo_thread) __builtin_amdgcn_s_setprio(PLBM_HALO_PRIO);
       if (halo_thread)
-        march_halo_mu();
+        march_halo();
       else
         march_mu(BoolC<false>{});
     } else {

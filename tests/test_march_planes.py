@@ -3,14 +3,17 @@
 The kernel's tile waves and halo waves walk a chunk [z0, z1) of z planes
 with one barrier per collided plane, loading each plane's populations ahead
 of use (one phase ahead, or a full plane iteration ahead) and writing its psi
-into a 4-plane LDS ring.  This test replays the same loop structure, in the
-same order, for both prefetch depths, periodic and walled axes, every axis
-length 1..9 and every chunk length, and checks:
+into a 4-plane LDS ring; the halo waves keep NH planes of loads in flight in
+NH rotating register sets, and the well-balanced scheme's chemical-potential
+pass runs its tile waves the same way (NM sets; its phase B reads only the
+ring).  This test replays the same loop structures, in the same order, for
+every prefetch depth the kernel can be built with, periodic and walled axes,
+every axis length 1..9 and every chunk length, and checks:
 
 * every stored plane the loads touch (the plane and its two neighbours) lies
-  in [0, nz): the march loads one (prefetch 1) or two (prefetch 2) planes past
-  the last one the collision needs, unconditionally, and a periodic axis
-  shorter than that window (nz = 1, 2) must still wrap inside the array;
+  in [0, nz): the march loads up to as many planes past the last one the
+  collision needs as it keeps in flight, unconditionally, and a periodic axis
+  shorter than that window (nz = 1, 2, 3) must still wrap inside the array;
 * a plane's psi is summed from the register set that was loaded with that
   plane, and a collided plane uses the set holding its own populations;
 * tile waves and halo waves meet the same number of barriers;
@@ -60,7 +63,10 @@ class Trace:
 
     def collide(self, z, regset):
         assert self.sets.get(regset) == z, f"plane {z} collided from set holding {self.sets.get(regset)}"
-        # the stencil reads psi of planes z - 1, z, z + 1 from their ring slots
+        self.stencil(z)
+
+    def stencil(self, z):
+        # the stencil reads the ring values of planes z - 1, z, z + 1 from their slots
         for zz in (z - 1, z, z + 1):
             self.reads.append((self.interval, (zz - self.z0 + 1) & 3, zz))
 
@@ -114,52 +120,66 @@ def tile_march(tr, prefetch):
             stepz(z, "fc", "fa", "fb")
 
 
-def halo_march(tr, prefetch):
+def rotating_march(tr, n, who, step_reads):
+    """n register sets, plane z0+2+j in set j mod n: iteration z issues plane z+1+n, passes the plane barrier,
+    (tile waves of the chemical-potential pass: evaluates the stencil of plane z,) and writes plane z+2."""
     z0, z1 = tr.z0, tr.z1
     for zl in range(z0 - 1, z0 + 2):
-        tr.issue(zl, "ha"); tr.finish(zl, "ha", "h")
+        tr.issue(zl, f"{who}0"); tr.finish(zl, f"{who}0", who)
+    for j in range(n - 1):
+        tr.issue(z0 + 2 + j, f"{who}{j}")
+
+    def step(z, u):
+        tr.issue(z + 1 + n, f"{who}{(u + n - 1) % n}")
+        tr.barrier()
+        if step_reads:
+            tr.stencil(z)
+        tr.finish(z + 2, f"{who}{u}", who)
+
     z = z0
-    if prefetch == 1:
-        while z < z1:
-            tr.issue(z + 2, "ha")
-            tr.barrier()
-            tr.finish(z + 2, "ha", "h")
-            z += 1
-    else:
-        tr.issue(z0 + 2, "ha")
-        while z + 1 < z1:
-            tr.issue(z + 3, "hb")
-            tr.barrier()
-            tr.finish(z + 2, "ha", "h")
-            tr.issue(z + 4, "ha")
-            tr.barrier()
-            tr.finish(z + 3, "hb", "h")
-            z += 2
-        if z < z1:
-            tr.issue(z + 3, "hb")
-            tr.barrier()
-            tr.finish(z + 2, "ha", "h")
+    while z + n - 1 < z1:
+        for u in range(n):
+            step(z + u, u)
+        z += n
+    for u in range(n - 1):
+        if z + u < z1:
+            step(z + u, u)
+
+
+def halo_march(tr, depth):
+    rotating_march(tr, depth, "h", False)
+
+
+def mu_march(tr, depth):
+    rotating_march(tr, depth, "t", True)
 
 
 def chunks(nz, cz):
     return [(z0, min(z0 + cz, nz)) for z0 in range(0, nz, cz)]
 
 
-@pytest.mark.parametrize("prefetch", [1, 2])
+# (tile waves: update march of prefetch 1 or 2, or the chemical-potential pass with n sets; halo waves: n sets)
+MARCHES = [("update", p, h) for p in (1, 2) for h in (1, 2, 3)] + [("mu", n, n) for n in (1, 2, 3, 4)]
+
+
+@pytest.mark.parametrize("kind,tile_depth,halo_depth", MARCHES)
 @pytest.mark.parametrize("walls", [False, True])
-def test_march_stays_in_bounds_and_race_free(prefetch, walls):
+def test_march_stays_in_bounds_and_race_free(kind, tile_depth, halo_depth, walls):
     for nz in range(1, 10):
         for cz in range(1, nz + 1):
             for z0, z1 in chunks(nz, cz):
                 tt = Trace(nz, walls, z0, z1)
-                tile_march(tt, prefetch)
+                if kind == "update":
+                    tile_march(tt, tile_depth)
+                else:
+                    mu_march(tt, tile_depth)
                 th = Trace(nz, walls, z0, z1)
-                halo_march(th, prefetch)
+                halo_march(th, halo_depth)
                 assert tt.interval == th.interval == z1 - z0
                 # every collided plane, in order
                 assert sorted({r[2] for r in tt.reads}) == list(range(z0 - 1, z1 + 1))
-                # at most one (prefetch 1) or two (prefetch 2) planes past the last one the collision reads
-                assert max(tt.loaded) <= z1 + prefetch and max(th.loaded) <= z1 + prefetch
+                # at most as many planes past the last one the collision reads as are kept in flight
+                assert max(tt.loaded) <= z1 + tile_depth and max(th.loaded) <= z1 + halo_depth
                 writes = tt.writes + th.writes
                 for k, slot, zz in tt.reads:
                     # no write to a slot in the interval it is read
@@ -171,8 +191,8 @@ def test_march_stays_in_bounds_and_race_free(prefetch, walls):
 
 
 def test_short_periodic_axis_wraps_inside_the_array():
-    # the window z0 - 1 .. z1 + 2 of a chunk, with neighbours, on axes of length 1 and 2
-    for nz in (1, 2):
-        for zl in range(-1, nz + 4):
+    # the window z0 - 1 .. z1 + 4 of a chunk, with neighbours, on axes of length 1 to 3
+    for nz in (1, 2, 3):
+        for zl in range(-1, nz + 6):
             p = wrapz(zl, nz, False)
             assert 0 <= p < nz and (p - zl) % nz == 0
