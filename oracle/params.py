@@ -207,7 +207,10 @@ def stability_integral(eos, p0, rv, rl, eps):
 def _bracketed_root(g, p_lo, p_hi):
     """Root of g on (p_lo, p_hi): the highest sign change on a geometric grid, then Brent."""
     grid = np.geomspace(max(p_lo, p_hi * 1e-8) * (1 + 1e-9), p_hi * (1 - 1e-9), 25)
-    vals = [g(p) for p in grid]
+    # at the lowest grid pressures the vapour root sits where psi underflows to
+    # zero and g is not finite; such points are skipped below
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        vals = [g(p) for p in grid]
     for k in reversed(range(len(grid) - 1)):
         if np.isfinite(vals[k]) and np.isfinite(vals[k + 1]) and vals[k] * vals[k + 1] <= 0:
             return optimize.brentq(g, grid[k], grid[k + 1], xtol=1e-16, rtol=1e-14, maxiter=500)
