@@ -12,6 +12,8 @@
    to round-off under the well-balanced scheme (float64), while the paper's
    discretisation of the same fluid keeps them; the settled droplet obeys
    Young-Laplace with the scheme's planar surface tension.
+4. Periodic marching axes of one to three planes (shorter than the planes
+   both launches load ahead) wrap inside an exact-size buffer.
 The fluid is the paper's EOS (R134a-like lattice densities 0.0375 / 1.187,
 interface width parameter xi = 3), gradient coefficient k = 0.15.
 """
@@ -176,3 +178,64 @@ def test_wb_lattices_are_not_batched():
     assert e.value.code == N.PLBM_E_UNSUPPORTED
     N.plbm_batch_destroy(b)
     lat.close()
+
+
+SHORT_AXES = [
+    # lattice, dims (the last axis is the kernel's marching axis), steps
+    ("D3Q19", (5, 3, 1), 3),
+    ("D3Q19", (5, 3, 2), 3),
+    ("D3Q19", (4, 3, 3), 4),
+    ("D2Q9", (7, 1), 3),
+    ("D2Q9", (7, 2), 4),
+]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("case", SHORT_AXES, ids=lambda c: f"{c[0]}-{'x'.join(map(str, c[1]))}")
+def test_wb_short_periodic_marching_axis_stays_inside_the_lattice(case, storage):
+    """Both launches of a well-balanced step load planes ahead of their use (the
+    chemical-potential pass three planes of populations, the update its mu
+    ring); a periodic marching axis shorter than that window must wrap inside
+    the lattice's arrays.  The lattice sits at the start of a buffer whose
+    remaining megabyte holds all-ones bytes (NaN in float32 and float64): a read
+    past the lattice would carry a NaN into the state (the reduction's NaN flag,
+    and parity); the bytes after the lattice stay untouched."""
+    require_gpu()
+    import torch
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import make_desc
+
+    lattice, dims, steps = case
+    fmt("wb_short_axis", case=case, storage=storage)
+    wb = _oracle(lattice, "mrt", False, 0.9, 1.1)
+    prm = N.plbm_params_paper_lattice(RV, RL, XI, 2.0, 1.0, 0.9, 1.1, [0.0, 0.0, 0.0])
+    desc = make_desc(lattice, dims, "mrt", storage, wb_k=K_GRAD, wb_rho0=RV)
+    nb = N.plbm_lattice_bytes(desc)
+    mem = torch.full((nb + 256 + (1 << 20),), 0xFF, dtype=torch.uint8, device="cuda")
+    ptr = (mem.data_ptr() + 255) // 256 * 256
+    stream = torch.cuda.Stream()
+    h = N.plbm_create(desc, prm, ptr, nb, stream.cuda_stream)
+    Q = LATTICES[lattice].Q
+    try:
+        co = syn.grid(dims)
+        rho = syn.droplet(co, dims, RV, RL, R=1.2, W=2.0, centre=[n / 2.0 for n in dims])
+        f_in = syn.random_populations(Q, co, dims, 41, rho, 0.05)
+        N.plbm_write_populations(h, f_in.reshape(-1))
+        ref = f_in if storage == "f64" else f_in.astype(np.float32).astype(np.float64)
+        for _ in range(steps):
+            d = N.plbm_reduce(h, True)
+            assert d.flags == 0, d.flags
+            N.plbm_step(h, 1)
+        d = N.plbm_reduce(h, True)
+        assert d.flags == 0, d.flags
+        ref = W.run(wb, ref, steps)
+        f = N.plbm_read_populations(h, Q, int(np.prod(dims))).reshape(ref.shape)
+        tf, _ = tols(storage, steps)
+        err = rel_max(f, ref)
+        fmt("wb_short_axis_err", err=f"{err:.3e}", tol=f"{tf:.3e}")
+        assert err <= tf
+        stream.synchronize()
+        assert bool((mem[ptr - mem.data_ptr() + nb:] == 0xFF).all())
+    finally:
+        stream.synchronize()
+        N.plbm_destroy(h)
