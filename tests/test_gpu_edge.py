@@ -91,11 +91,13 @@ SHORT_AXES = [
 ]
 
 
+@pytest.mark.parametrize("pattern", ["ab", "aa"])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s", "f16r", "bf16r"])
 @pytest.mark.parametrize("case", SHORT_AXES, ids=lambda c: f"{c[0]}-{'x'.join(map(str, c[1]))}")
-def test_short_periodic_marching_axis_reads_stay_inside_the_lattice(case, storage):
+def test_short_periodic_marching_axis_reads_stay_inside_the_lattice(case, storage, pattern):
     """A periodic marching axis shorter than the march's load window (one to
-    three planes) must wrap inside the population arrays.  The lattice sits at
+    three planes) must wrap inside the population arrays (both patterns: the
+    in-place update loads the psi ring a plane ahead).  The lattice sits at
     the start of a buffer whose remaining megabyte holds all-ones bytes (NaN
     in every storage format): a load past the lattice's own bytes would sum a
     NaN density, whose psi radicand raises the PSI_NEG flag of the reduction
@@ -111,11 +113,11 @@ def test_short_periodic_marching_axis_reads_stay_inside_the_lattice(case, storag
     from gpu_cases import ULP, storage_round
 
     lattice, dims, steps = case
-    fmt("edge_short_axis", case=case, storage=storage)
+    fmt("edge_short_axis", case=case, storage=storage, pattern=pattern)
     op = oracle_params(lattice, collision="mrt")
     rl = op.rho_l
     shifted = storage in ("f16s", "bf16s")
-    desc = make_desc(lattice, dims, "mrt", storage, rho0_shift=rl if shifted else 0.0)
+    desc = make_desc(lattice, dims, "mrt", storage, rho0_shift=rl if shifted else 0.0, pattern=pattern)
     nb = N.plbm_lattice_bytes(desc)
     pad = 1 << 20
     mem = torch.full((nb + 256 + pad,), 0xFF, dtype=torch.uint8, device="cuda")
