@@ -329,11 +329,15 @@ def precision_run(torch, N, Lattice, steps):
             "storages": rows}
 
 
-def serve_run(N, seconds, budget_gb, collision="mrt"):
+CHANNELS = dict(width2d=(64, 512), width3d=(64, 192), channel_len=8, body_force=1e-6)
+
+
+def serve_run(N, seconds, budget_gb, collision="mrt", channel_frac=0.0):
     """Continuous-batching serving of the Poisson request stream (50 req/s, 500 requests, seed 0): D2Q9 64^2 to
     1024^2 and D3Q19 64^3 to 192^3 droplets, T/Tc in [0.6, 0.9], radius [0.15, 0.35] of the side, f32, BGK or
-    MRT, converged at max|du|/step <= 1e-8 over 100 steps.  Then a second stream at 0.8 x the measured
-    capacity."""
+    MRT, converged at max|du|/step <= 1e-8 over 100 steps; with channel_frac > 0 that share of the requests are
+    two-phase channels instead (width 64..512 in 2-D, 64..192 in 3-D, 8 nodes along the other axes, body force
+    1e-6 along x).  Then a second stream at 0.8 x the measured capacity."""
     import plbm_synth as syn
     from paper_2504_15018_amd.serving import Server, from_synth
 
@@ -352,14 +356,16 @@ def serve_run(N, seconds, budget_gb, collision="mrt"):
         out.pop("records")
         return out
 
-    first = one(from_synth(syn.request_stream(500, 50.0, seed=0)), "c5")
+    first = one(from_synth(syn.request_stream(500, 50.0, seed=0, channel_frac=channel_frac, **CHANNELS)), "c5")
     cap = first["solves_per_s"]
     rate = max(0.8 * cap, 1e-3)
-    second = one(from_synth(syn.request_stream(max(4, int(rate * seconds * 1.2)), rate, seed=1)), "sustainable")
-    return {"collision": collision, "stream": first, "sustainable": dict(second, rate_per_s=rate)}
+    second = one(from_synth(syn.request_stream(max(4, int(rate * seconds * 1.2)), rate, seed=1,
+                                               channel_frac=channel_frac, **CHANNELS)), "sustainable")
+    return {"collision": collision, "channel_frac": channel_frac, "stream": first,
+            "sustainable": dict(second, rate_per_s=rate)}
 
 
-def serving_leg(N, seconds=40.0, rate=0.5, seed=1, check_seconds=25.0, budget_gb=240.0):
+def serving_leg(N, seconds=40.0, rate=0.5, seed=1, check_seconds=25.0, budget_gb=240.0, channel_frac=0.0):
     """Serving form at a sustainable rate, bounded: Poisson arrivals of the C5 mix for `seconds`, float32 MRT,
     converged at max|du|/step <= 1e-8 over 100 steps; then the cheapest converged requests solved again alone
     in float64 (within `check_seconds`) to state the served results' accuracy (droplet densities at the
@@ -367,7 +373,8 @@ def serving_leg(N, seconds=40.0, rate=0.5, seed=1, check_seconds=25.0, budget_gb
     import plbm_synth as syn
     from paper_2504_15018_amd.serving import Server, from_synth, solve_alone
 
-    reqs = from_synth(syn.request_stream(max(4, int(rate * seconds * 1.2)), rate, seed=seed))
+    reqs = from_synth(syn.request_stream(max(4, int(rate * seconds * 1.2)), rate, seed=seed,
+                                         channel_frac=channel_frac, **CHANNELS))
     srv = Server(budget_bytes=int(budget_gb * 1e9), max_slots=64, max_tiles=1 << 21, check_every=100, tol=1e-8,
                  max_steps=2_000_000, collision="mrt", record_results=True)
     out = srv.run(reqs, time_limit=seconds)
@@ -384,8 +391,8 @@ def serving_leg(N, seconds=40.0, rate=0.5, seed=1, check_seconds=25.0, budget_gb
             continue
         st, steps, ref = solve_alone(r, storage="f64", collision="mrt", tol=1e-8, max_steps=2 * r.steps + 1000,
                                      time_limit=left)
-        row = {"lattice": r.lattice, "side": r.dims[0], "T_over_Tc": round(r.T_over_Tc, 4), "steps_f32": r.steps,
-               "steps_f64": steps, "f64_status": st}
+        row = {"lattice": r.lattice, "problem": r.problem, "dims": list(r.dims), "T_over_Tc": round(r.T_over_Tc, 4),
+               "steps_f32": r.steps, "steps_f64": steps, "f64_status": st}
         if st == "converged":
             row["rho_in_rel_err"] = abs(r.result["rho_in"] - ref["rho_in"]) / ref["rho_in"]
             row["rho_out_rel_err"] = abs(r.result["rho_out"] - ref["rho_out"]) / ref["rho_out"]
@@ -397,7 +404,9 @@ def serving_leg(N, seconds=40.0, rate=0.5, seed=1, check_seconds=25.0, budget_gb
     out.update({
         "workload": f"Poisson arrivals at {rate} requests/s for {seconds:g} s (seed {seed}): D2Q9 64^2..1024^2 and "
                     f"D3Q19 64^3..192^3 static droplets, Peng-Robinson T/Tc in [0.6, 0.9], radius 0.15..0.35 of "
-                    f"the side, f32 storage, MRT, converged at max|du|/step <= 1e-8 over 100 steps",
+                    f"the side, f32 storage, MRT, converged at max|du|/step <= 1e-8 over 100 steps"
+                    + (f"; {channel_frac:g} of the requests two-phase channels (width 64..512 / 64..192, 8 nodes "
+                       f"along the other axes, body force 1e-6)" if channel_frac > 0 else ""),
         "rate_per_s": rate, "window_s": seconds,
         "accuracy_vs_f64": {"checked": len(ok), "max_coexistence_density_rel_err": worst, "bar": 1e-3,
                             "cases": cases},
@@ -441,6 +450,8 @@ def main():
                     help="length of the bounded serving leg (0 skips it)")
     ap.add_argument("--serve-first", type=int, default=1,
                     help="1 (default): run the serving leg before the step benchmark; 0: after it")
+    ap.add_argument("--serve-channel-frac", type=float, default=0.0,
+                    help="share of the served requests that are two-phase channels (width sweep) instead of droplets")
     ap.add_argument("--serve-collision", default="mrt", choices=["bgk", "mrt"],
                     help="collision of the served lattices (MRT: fewer unstable requests at low T/Tc)")
     args = ap.parse_args()
@@ -471,13 +482,14 @@ def main():
         return
     if args.serve:
         print(json.dumps({"metric": "solves/s + p50/p99 time to converged solution",
-                          **serve_run(N, args.serve_seconds, args.serve_budget_gb, args.serve_collision)}),
+                          **serve_run(N, args.serve_seconds, args.serve_budget_gb, args.serve_collision,
+                                      args.serve_channel_frac)}),
               flush=True)
         return
     serving = None
 
     def run_serving_leg():
-        out = serving_leg(N, seconds=args.serve_leg_seconds)
+        out = serving_leg(N, seconds=args.serve_leg_seconds, channel_frac=args.serve_channel_frac)
         log(f"[bench] serving leg: {out['converged']} converged, {out['solves_per_s']} solves/s, "
             f"p50 {out['latency_p50_s']} s, p99 {out['latency_p99_s']} s")
         torch.cuda.empty_cache()

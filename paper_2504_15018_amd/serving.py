@@ -1,7 +1,10 @@
 """Continuous-batching request loop for P-LBM solves (plbm_batch_*).
 
-A request asks for one static-droplet solve: lattice kind and size, reduced
-temperature of the lattice Peng-Robinson EOS, droplet radius.  The loop
+A request asks for one solve: lattice kind and size, reduced temperature of
+the lattice Peng-Robinson EOS, and the problem: a static droplet of a given
+radius (periodic box), or a two-phase channel (liquid below vapour between
+half-way bounce-back walls on the last axis, whose extent is the channel
+width, driven by a body force along x).  The loop
 
   * admits queued requests in arrival order while a batch slot is free and the
     device bytes of every resident lattice (plbm_lattice_bytes) plus the new
@@ -21,9 +24,11 @@ temperature of the lattice Peng-Robinson EOS, droplet radius.  The loop
 Every lattice's result is bitwise the same as stepping it alone: the batch
 only changes which workgroup computes which tile.  With `record_results`, a
 converged lattice's droplet densities (centre and far corner) and maximum
-speed are read on the device before it is released; `solve_alone` runs one
-request by itself on the plain single-lattice path (any storage, e.g. float64)
-to the same convergence test, for comparison with the served result.
+speed are read on the device before it is released (a channel's liquid and
+vapour layer densities and its peak speed); `solve_alone` runs one request by
+itself on the plain single-lattice path (any storage, e.g. float64) to the
+same convergence test, for comparison with the served result.  Both set a
+request up with `setup_lattice`.
 """
 import time
 
@@ -34,13 +39,17 @@ from .lattice import Lattice
 
 
 class Request:
-    def __init__(self, rid, arrival, lattice, dims, T_over_Tc, radius):
+    def __init__(self, rid, arrival, lattice, dims, T_over_Tc, radius, problem="droplet", body_force=0.0):
+        if problem not in ("droplet", "channel"):
+            raise ValueError(f"unknown problem {problem!r}")
         self.id = rid
         self.arrival = float(arrival)
         self.lattice = lattice
         self.dims = tuple(int(v) for v in dims)
         self.T_over_Tc = float(T_over_Tc)
         self.radius = float(radius)
+        self.problem = problem
+        self.body_force = float(body_force)  # channel: along x, lattice units
         self.admit = None
         self.done = None
         self.steps = 0
@@ -51,7 +60,7 @@ class Request:
         self.slot = None
         self.params = None
         self.error = None
-        self.result = None  # droplet densities and max|u| at convergence (record_results)
+        self.result = None  # rho_in / rho_out and max|u| at convergence (record_results)
 
     @property
     def nodes(self):
@@ -61,25 +70,61 @@ class Request:
         return {"id": self.id, "arrival": self.arrival, "admit": self.admit, "done": self.done,
                 "latency": None if self.done is None else self.done - self.arrival, "steps": self.steps,
                 "status": self.status, "bytes": self.bytes, "nodes": self.nodes, "lattice": self.lattice,
-                "dims": self.dims, "T_over_Tc": self.T_over_Tc, "residual": self.residual, "error": self.error,
-                "result": self.result}
+                "dims": self.dims, "T_over_Tc": self.T_over_Tc, "problem": self.problem,
+                "residual": self.residual, "error": self.error, "result": self.result}
+
+    @property
+    def walls(self):
+        return self.problem == "channel"
 
 
-def droplet_readout(torch, lat, dims, max_u):
-    """Densities at the droplet centre (node dims // 2) and in the far field (node 0), from the moments of the
-    lattice's current state computed on the device; lat's stream must be idle or own the work before it."""
+def setup_lattice(req, storage, collision, stream=None, pattern="ab", width=5.0):
+    """The request's lattice parameters and its initialised lattice: a tanh droplet of the request's radius
+    at the box centre, or liquid below vapour at half the channel width (tanh width `width`) between walls on
+    the last axis with the body force along x."""
+    bf = [req.body_force, 0.0, 0.0] if req.walls else None
+    prm = N.plbm_params_pr_lattice(req.T_over_Tc, 0.326, 2.0, 1.0, 1.0, 1.0, bf)
+    lat = Lattice(req.lattice, req.dims, prm, collision=collision, storage=storage, stream=stream, pattern=pattern,
+                  walls=req.walls)
+    try:
+        if req.walls:
+            ax = len(req.dims) - 1
+            lat.init_shape(N.PLBM_SHAPE_LAYERS, prm.rho_l, prm.rho_v, W=width, level=req.dims[ax] / 2.0, axis=ax)
+        else:
+            lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=width, R=req.radius,
+                           centre=[n / 2.0 for n in req.dims])
+    except BaseException:
+        lat.close()
+        raise
+    return prm, lat
+
+
+def result_readout(torch, lat, req, max_u):
+    """The two coexisting densities of the request's current state, from its moments computed on the device:
+    a droplet's centre (node dims // 2, rho_in) and far field (node 0, rho_out); a channel's liquid and vapour
+    layers at a quarter and three quarters of the width (lateral node 0).  lat's stream must be idle or own
+    the work before it."""
+    dims = req.dims
     n = int(np.prod(dims))
     d = len(dims)
     rho = torch.empty(n, dtype=torch.float64, device="cuda")
     u = torch.empty(d * n, dtype=torch.float64, device="cuda")
     N.plbm_moments_device(lat.h, rho.data_ptr(), u.data_ptr())
     lat.stream.synchronize()
-    centre = 0
-    stride = 1
-    for ext in dims:
-        centre += (ext // 2) * stride
-        stride *= ext
-    return {"rho_in": float(rho[centre].item()), "rho_out": float(rho[0].item()), "max_u": float(max_u)}
+
+    def flat(idx):  # x fastest
+        k, stride = 0, 1
+        for i, ext in zip(idx, dims):
+            k += i * stride
+            stride *= ext
+        return k
+
+    if req.walls:
+        h = dims[-1]
+        i_in, i_out = flat((0,) * (d - 1) + (h // 4,)), flat((0,) * (d - 1) + ((3 * h) // 4,))
+    else:
+        i_in, i_out = flat([ext // 2 for ext in dims]), 0
+    return {"rho_in": float(rho[i_in].item()), "rho_out": float(rho[i_out].item()), "max_u": float(max_u)}
 
 
 def solve_alone(req, storage="f64", collision="mrt", check_every=100, tol=1e-8, max_steps=2_000_000, width=5.0,
@@ -88,12 +133,9 @@ def solve_alone(req, storage="f64", collision="mrt", check_every=100, tol=1e-8, 
     max|u(t) - u(t-k)|/k is at or below tol; returns (status, steps, result)."""
     import torch
 
-    prm = N.plbm_params_pr_lattice(req.T_over_Tc, 0.326, 2.0, 1.0, 1.0, 1.0)
-    lat = Lattice(req.lattice, req.dims, prm, collision=collision, storage=storage)
+    _, lat = setup_lattice(req, storage, collision, width=width)
     t0 = time.perf_counter()
     try:
-        lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=width, R=req.radius,
-                       centre=[n / 2.0 for n in req.dims])
         lat.reduce()
         steps, status, d = 0, "capped", None
         while steps < max_steps:
@@ -109,7 +151,7 @@ def solve_alone(req, storage="f64", collision="mrt", check_every=100, tol=1e-8, 
             if time_limit is not None and time.perf_counter() - t0 > time_limit:
                 status = "timeout"
                 break
-        res = droplet_readout(torch, lat, req.dims, d.max_u if d is not None else 0.0)
+        res = result_readout(torch, lat, req, d.max_u if d is not None else 0.0)
         return status, steps, res
     finally:
         lat.close()
@@ -131,7 +173,8 @@ def admissible(queue, n_resident, used, budget, max_slots):
 
 
 def from_synth(reqs):
-    return [Request(r["id"], r["arrival"], r["lattice"], r["dims"], r["T_over_Tc"], r["radius"]) for r in reqs]
+    return [Request(r["id"], r["arrival"], r["lattice"], r["dims"], r["T_over_Tc"], r["radius"],
+                    r.get("problem", "droplet"), r.get("body_force", 0.0)) for r in reqs]
 
 
 class Lane:
@@ -216,16 +259,12 @@ class Server:
     def _desc_bytes(self, req):
         from .lattice import make_desc
         return N.plbm_lattice_bytes(make_desc(req.lattice, req.dims, self.collision, self.storage,
-                                              pattern=self.pattern)) + 256
+                                              walls=req.walls, pattern=self.pattern)) + 256
 
     def _admit(self, lane, req, now):
-        req.params = N.plbm_params_pr_lattice(req.T_over_Tc, 0.326, 2.0, 1.0, 1.0, 1.0)
-        lat = Lattice(req.lattice, req.dims, req.params, collision=self.collision, storage=self.storage,
-                      stream=lane.stream, pattern=self.pattern)
+        req.params, lat = setup_lattice(req, self.storage, self.collision, stream=lane.stream, pattern=self.pattern,
+                                        width=self.width)
         req.lat = lat
-        centre = [n / 2.0 for n in req.dims]
-        lat.init_shape(N.PLBM_SHAPE_DROPLET, req.params.rho_l, req.params.rho_v, W=self.width, R=req.radius,
-                       centre=centre)
         lat.reduce()  # stores u(0) for the first residual
         req.slot = N.plbm_batch_attach(lane.batch, lat.h)
         req.admit = now
@@ -237,7 +276,7 @@ class Server:
 
     def _retire(self, lane, req, status, now, max_u=0.0):
         if status == "converged" and self.record_results:
-            req.result = droplet_readout(self.torch, req.lat, req.dims, max_u)
+            req.result = result_readout(self.torch, req.lat, req, max_u)
         N.plbm_batch_detach(lane.batch, req.slot)
         del lane.resident[req.slot]
         req.status = status

@@ -124,8 +124,12 @@ def window(dims, lo, size):
 # ----------------------------------------------------------------------------
 # serving workload: a Poisson stream of uneven requests
 
-def request_stream(n, rate, seed=0, side2d=(64, 1024), side3d=(64, 192), t_range=(0.6, 0.9), r_frac=(0.15, 0.35)):
-    """List of dicts: arrival time, lattice type, sides, T/Tc, radius."""
+def request_stream(n, rate, seed=0, side2d=(64, 1024), side3d=(64, 192), t_range=(0.6, 0.9), r_frac=(0.15, 0.35),
+                   channel_frac=0.0, width2d=(64, 512), width3d=(64, 192), channel_len=8, body_force=1e-6):
+    """List of dicts: arrival time, lattice type, sides, T/Tc, and the problem: a static droplet (radius), or,
+    with probability channel_frac, a two-phase channel between walls on the last axis (width = that axis,
+    channel_len nodes along the others, body force along x).  The droplet draws do not depend on
+    channel_frac."""
     k = np.arange(n, dtype=np.uint64)
     gaps = -np.log(1.0 - uniform01(seed, 1, k)) / rate
     arrivals = np.cumsum(gaps)
@@ -133,22 +137,23 @@ def request_stream(n, rate, seed=0, side2d=(64, 1024), side3d=(64, 192), t_range
     u_side = uniform01(seed, 3, k)
     u_t = uniform01(seed, 4, k)
     u_r = uniform01(seed, 5, k)
+    chan = uniform01(seed, 6, k) < channel_frac
     out = []
     for i in range(n):
-        if kind[i]:
-            lo, hi = side2d
-            side = int(lo + np.floor(u_side[i] * (hi - lo + 1)))
-            dims = (side, side)
+        lo, hi = (width2d if kind[i] else width3d) if chan[i] else (side2d if kind[i] else side3d)
+        side = int(lo + np.floor(u_side[i] * (hi - lo + 1)))
+        if chan[i]:
+            dims = (channel_len, side) if kind[i] else (channel_len, channel_len, side)
         else:
-            lo, hi = side3d
-            side = int(lo + np.floor(u_side[i] * (hi - lo + 1)))
-            dims = (side, side, side)
+            dims = (side, side) if kind[i] else (side, side, side)
         out.append({
             "id": i,
             "arrival": float(arrivals[i]),
             "lattice": "D2Q9" if kind[i] else "D3Q19",
             "dims": dims,
             "T_over_Tc": float(t_range[0] + u_t[i] * (t_range[1] - t_range[0])),
-            "radius": float((r_frac[0] + u_r[i] * (r_frac[1] - r_frac[0])) * side),
+            "radius": 0.0 if chan[i] else float((r_frac[0] + u_r[i] * (r_frac[1] - r_frac[0])) * side),
+            "problem": "channel" if chan[i] else "droplet",
+            "body_force": float(body_force) if chan[i] else 0.0,
         })
     return out

@@ -151,3 +151,46 @@ def test_a_request_cancelled_mid_flight_leaves_the_rest_intact():
         r.lat.close()
     victim.lat.close()
     srv.close()
+
+
+def test_served_channels_and_droplets_match_solo_runs_and_the_fp64_method():
+    """A stream that sweeps channel width as well as droplet size (two-phase channels between walls, driven
+    along x, beside periodic droplets, in the same lanes: the batch launches walled and periodic lattices as
+    separate groups).  Each served result (f32, MRT, converged at max|du|/step <= 1e-8) is bitwise the same as
+    the request run alone for the same number of steps, and its two coexisting densities (a channel's liquid
+    and vapour layers) agree with the plain float64 method, solved alone to the same test, within 1e-3; the
+    peak speed is reported beside them."""
+    require_gpu()
+    import plbm_synth as syn
+    from paper_2504_15018_amd.serving import Server, from_synth, setup_lattice, solve_alone
+
+    fmt("serving_channels")
+    reqs = from_synth(syn.request_stream(8, 100.0, seed=24, side2d=(40, 64), side3d=(20, 28), t_range=(0.78, 0.85),
+                                         r_frac=(0.3, 0.35), channel_frac=0.5, width2d=(24, 48), width3d=(16, 32),
+                                         channel_len=8, body_force=1e-6))
+    assert {(r.problem, r.lattice) for r in reqs} == {(p, k) for p in ("droplet", "channel") for k in ("D2Q9", "D3Q19")}
+    srv = Server(budget_bytes=1 << 34, max_slots=8, max_tiles=1 << 16, check_every=100, tol=1e-8,
+                 max_steps=300_000, collision="mrt", record_results=True, keep_lattices=True)
+    out = srv.run(reqs, time_limit=150)
+    print({k: v for k, v in out.items() if k != "records"}, flush=True)
+    assert out["unfinished"] == 0 and out["failed"] == 0 and out["rejected"] == 0
+    worst = 0.0
+    for r in reqs:
+        assert r.status == "converged", r.record()
+        _, solo = setup_lattice(r, "f32", "mrt")
+        solo.step(r.steps)
+        assert np.array_equal(solo.populations(), r.lat.populations()), r.record()
+        solo.close()
+        r.lat.close()
+        st, steps, ref = solve_alone(r, storage="f64", collision="mrt", tol=1e-8, max_steps=300_000)
+        assert st == "converged", (r.record(), st, steps)
+        e_in = abs(r.result["rho_in"] - ref["rho_in"]) / ref["rho_in"]
+        e_out = abs(r.result["rho_out"] - ref["rho_out"]) / ref["rho_out"]
+        fmt("serving_channels_case", id=r.id, problem=r.problem, lattice=r.lattice, dims=r.dims,
+            T=f"{r.T_over_Tc:.3f}", steps_f32=r.steps, steps_f64=steps, rho_in_err=f"{e_in:.2e}",
+            rho_out_err=f"{e_out:.2e}", max_u=f"{ref['max_u']:.3e}",
+            max_u_err=f"{abs(r.result['max_u'] - ref['max_u']) / ref['max_u']:.2e}")
+        worst = max(worst, e_in, e_out)
+        assert ref["rho_in"] > 5 * ref["rho_out"]  # the droplet, or the liquid layer below the vapour, persists
+    assert worst <= 1e-3
+    srv.close()

@@ -3,7 +3,7 @@ a slot limit, and the request stream it is fed (no GPU needed)."""
 import numpy as np
 
 import plbm_synth as syn
-from paper_2504_15018_amd.serving import Request, admissible, summarize
+from paper_2504_15018_amd.serving import Request, admissible, from_synth, summarize
 
 
 def _req(i, nbytes, arrival=0.0):
@@ -67,3 +67,32 @@ def test_request_stream_statistics():
         assert 0.15 * side <= r["radius"] <= 0.35 * side
     # fixed seed: same stream twice
     assert syn.request_stream(10, 50.0, seed=0) == syn.request_stream(10, 50.0, seed=0)
+    assert all(r["problem"] == "droplet" for r in reqs)
+
+
+def test_request_stream_with_channels():
+    """A channel fraction turns that share of the requests into channels between walls (width on the last axis,
+    channel_len nodes along the others, the body force along x); the droplet requests of the same seed are
+    unchanged."""
+    base = syn.request_stream(400, 50.0, seed=2)
+    mixed = syn.request_stream(400, 50.0, seed=2, channel_frac=0.3, width2d=(32, 96), width3d=(24, 48),
+                               channel_len=6, body_force=2e-6)
+    chans = [r for r in mixed if r["problem"] == "channel"]
+    assert 0.2 < len(chans) / len(mixed) < 0.4
+    for r, b in zip(mixed, base):
+        assert r["arrival"] == b["arrival"] and r["lattice"] == b["lattice"] and r["T_over_Tc"] == b["T_over_Tc"]
+        if r["problem"] == "droplet":
+            assert r == b
+        else:
+            lo, hi = (32, 96) if r["lattice"] == "D2Q9" else (24, 48)
+            assert lo <= r["dims"][-1] <= hi and all(v == 6 for v in r["dims"][:-1])
+            assert len(r["dims"]) == (2 if r["lattice"] == "D2Q9" else 3)
+            assert r["body_force"] == 2e-6 and r["radius"] == 0.0
+    req = from_synth(chans[:1])[0]
+    assert req.problem == "channel" and req.walls and req.body_force == 2e-6
+
+
+def test_unknown_problem_is_refused():
+    import pytest
+    with pytest.raises(ValueError):
+        Request(0, 0.0, "D2Q9", (8, 8), 0.8, 2.0, problem="bubble")
