@@ -220,6 +220,9 @@ def stream_probe(torch, nodes=256 ** 3, reps=50):
     lib.plbm_probe_stream19v.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int,
                                          ctypes.c_void_p]
     lib.plbm_probe_copy4u.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+    lib.plbm_probe_stream19s.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_void_p]
+    lib.plbm_probe_copy4nt.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
     lib.plbm_probe_stream19x.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_void_p]
     moved = 2 * 19 * 4 * nodes
@@ -233,7 +236,12 @@ def stream_probe(torch, nodes=256 ** 3, reps=50):
             ("stream19_blocks_of_128", lambda: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, 128, 1, sp)),
             ("stream19_blocks_of_128_2_per_thread",
              lambda: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, 128, 2, sp)),
+            ("stream19_plain_stores", lambda: lib.plbm_probe_stream19s(a.data_ptr(), b.data_ptr(), nodes, 0, 0, sp)),
+            ("stream19_plain_stores_interleaved",
+             lambda: lib.plbm_probe_stream19s(a.data_ptr(), b.data_ptr(), nodes, 0, 1, sp)),
+            ("stream19_interleaved", lambda: lib.plbm_probe_stream19s(a.data_ptr(), b.data_ptr(), nodes, 1, 1, sp)),
             ("copy4", lambda: lib.plbm_probe_copy4(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp)),
+            ("copy4_nontemporal", lambda: lib.plbm_probe_copy4nt(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp)),
             ("copy4_4_per_thread", lambda: lib.plbm_probe_copy4u(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp))]
     for name, fn in runs:
         t = timed(fn)

@@ -12,6 +12,10 @@
 // nodes per thread (8- or 16-byte accesses per direction).
 // k_probe_stream19x<XB, V>: the same bytes in blocks of XB = 32, 64 or 128
 // nodes (128, 256 or 512 bytes per direction), V = 1 or 2 nodes per thread.
+// k_probe_stream19s<NT, ORDER>: blocks of 32 nodes, one node per thread, with
+// plain (NT = 0) or non-temporal stores, all loads before the stores
+// (ORDER = 0) or each direction stored right after its load (ORDER = 1).
+// k_probe_copy4nt: the float4 copy with non-temporal stores.
 // k_probe_copy4: a plain float4 copy, one vector per thread;
 // k_probe_copy4u: the same with four vectors per thread (a block-stride loop).
 #include <hip/hip_runtime.h>
@@ -62,6 +66,35 @@ __global__ __launch_bounds__(256) void k_probe_stream19x(const float* __restrict
 #pragma unroll
   for (int q = 0; q < kQ; ++q)
     __builtin_nontemporal_store(v[q] + 1.0f, reinterpret_cast<vec*>(dst + at + (uint64_t)q * XB));
+}
+
+template <int NTS, int ORDER>
+__global__ __launch_bounds__(256) void k_probe_stream19s(const float* __restrict__ src, float* __restrict__ dst,
+                                                         uint32_t nodes) {
+  const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+  if (n >= nodes) return;
+  const uint64_t at = (uint64_t)(n / kXB) * (kQ * kXB) + (n % kXB);
+  auto put = [&](int q, float v) {
+    if constexpr (NTS) __builtin_nontemporal_store(v, dst + at + (uint64_t)q * kXB);
+    else dst[at + (uint64_t)q * kXB] = v;
+  };
+  if constexpr (ORDER == 0) {
+    float v[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) v[q] = src[at + (uint64_t)q * kXB];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) put(q, v[q] + 1.0f);
+  } else {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) put(q, src[at + (uint64_t)q * kXB] + 1.0f);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_probe_copy4nt(const float* __restrict__ src, float* __restrict__ dst,
+                                                       uint64_t n) {
+  typedef float vec __attribute__((ext_vector_type(4)));
+  const uint64_t i = blockIdx.x * 256ull + threadIdx.x;
+  if (i < n) __builtin_nontemporal_store(reinterpret_cast<const vec*>(src)[i], reinterpret_cast<vec*>(dst) + i);
 }
 
 __global__ __launch_bounds__(256) void k_probe_copy4u(const float4* __restrict__ src, float4* __restrict__ dst,
@@ -128,6 +161,31 @@ int plbm_probe_stream19x(const void* src, void* dst, uint32_t nodes, int xb, int
   if (xb == 64 && vec == 2) hipLaunchKernelGGL((k_probe_stream19x<64, 2>), g, b, 0, st, s, d, nodes);
   if (xb == 128 && vec == 1) hipLaunchKernelGGL((k_probe_stream19x<128, 1>), g, b, 0, st, s, d, nodes);
   if (xb == 128 && vec == 2) hipLaunchKernelGGL((k_probe_stream19x<128, 2>), g, b, 0, st, s, d, nodes);
+  return (int)hipGetLastError();
+}
+
+// Blocks of 32 nodes, one node per thread; nt: non-temporal stores; order 0:
+// all loads, then the stores; order 1: each direction stored after its load.
+int plbm_probe_stream19s(const void* src, void* dst, uint32_t nodes, int nt, int order, void* stream) {
+  if (nodes == 0) return 0;
+  const dim3 g((nodes + 255u) / 256u), b(256);
+  const hipStream_t st = (hipStream_t)stream;
+  const float* s = (const float*)src;
+  float* d = (float*)dst;
+  if (!nt && !order) hipLaunchKernelGGL((k_probe_stream19s<0, 0>), g, b, 0, st, s, d, nodes);
+  if (!nt && order) hipLaunchKernelGGL((k_probe_stream19s<0, 1>), g, b, 0, st, s, d, nodes);
+  if (nt && !order) hipLaunchKernelGGL((k_probe_stream19s<1, 0>), g, b, 0, st, s, d, nodes);
+  if (nt && order) hipLaunchKernelGGL((k_probe_stream19s<1, 1>), g, b, 0, st, s, d, nodes);
+  return (int)hipGetLastError();
+}
+
+// The float4 copy with non-temporal stores; bytes a multiple of 16 below 2^43.
+int plbm_probe_copy4nt(const void* src, void* dst, uint64_t bytes, void* stream) {
+  const uint64_t n = bytes / 16;
+  if (n == 0) return 0;
+  if ((n + 255) / 256 > 0x7fffffffull) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_probe_copy4nt, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     (const float*)src, (float*)dst, n);
   return (int)hipGetLastError();
 }
 
