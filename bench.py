@@ -222,6 +222,8 @@ def stream_probe(torch, nodes=256 ** 3, reps=50):
     lib.plbm_probe_copy4u.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
     lib.plbm_probe_stream19s.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_void_p]
+    lib.plbm_probe_stream19h.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int,
+                                         ctypes.c_void_p]
     lib.plbm_probe_copy4nt.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
     lib.plbm_probe_stream19x.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_void_p]
@@ -241,12 +243,16 @@ def stream_probe(torch, nodes=256 ** 3, reps=50):
              lambda: lib.plbm_probe_stream19s(a.data_ptr(), b.data_ptr(), nodes, 0, 1, sp)),
             ("stream19_interleaved", lambda: lib.plbm_probe_stream19s(a.data_ptr(), b.data_ptr(), nodes, 1, 1, sp)),
             ("copy4", lambda: lib.plbm_probe_copy4(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp)),
+            # 16-bit populations: half the bytes (the rates below are of those bytes)
+            ("half_stream19", lambda: lib.plbm_probe_stream19h(a.data_ptr(), b.data_ptr(), nodes, 1, sp)),
+            ("half_stream19_2_per_thread", lambda: lib.plbm_probe_stream19h(a.data_ptr(), b.data_ptr(), nodes, 2, sp)),
+            ("half_stream19_4_per_thread", lambda: lib.plbm_probe_stream19h(a.data_ptr(), b.data_ptr(), nodes, 4, sp)),
             ("copy4_nontemporal", lambda: lib.plbm_probe_copy4nt(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp)),
             ("copy4_4_per_thread", lambda: lib.plbm_probe_copy4u(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp))]
     for name, fn in runs:
         t = timed(fn)
         out[name + "_us"] = round(t * 1e6, 1)
-        out[name + "_GBps"] = round(moved / t / 1e9, 1)
+        out[name + "_GBps"] = round((moved // 2 if name.startswith("half_") else moved) / t / 1e9, 1)
     return out
 
 

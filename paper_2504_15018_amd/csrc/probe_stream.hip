@@ -16,6 +16,9 @@
 // plain (NT = 0) or non-temporal stores, all loads before the stores
 // (ORDER = 0) or each direction stored right after its load (ORDER = 1).
 // k_probe_copy4nt: the float4 copy with non-temporal stores.
+// k_probe_stream19h<V>: 19 arrays of 16-bit values in blocks of 64 nodes (128
+// bytes per direction), V = 1, 2 or 4 consecutive nodes per thread (2-, 4- or
+// 8-byte accesses), non-temporal stores: the 16-bit update's bytes.
 // k_probe_copy4: a plain float4 copy, one vector per thread;
 // k_probe_copy4u: the same with four vectors per thread (a block-stride loop).
 #include <hip/hip_runtime.h>
@@ -97,6 +100,22 @@ __global__ __launch_bounds__(256) void k_probe_copy4nt(const float* __restrict__
   if (i < n) __builtin_nontemporal_store(reinterpret_cast<const vec*>(src)[i], reinterpret_cast<vec*>(dst) + i);
 }
 
+template <int V>
+__global__ __launch_bounds__(256) void k_probe_stream19h(const uint16_t* __restrict__ src, uint16_t* __restrict__ dst,
+                                                         uint32_t nodes) {
+  constexpr int XB = 64;
+  typedef uint16_t vec __attribute__((ext_vector_type(V)));
+  const uint32_t n = (blockIdx.x * 256u + threadIdx.x) * V;
+  if (n >= nodes) return;
+  const uint64_t at = (uint64_t)(n / XB) * (kQ * XB) + (n % XB);
+  vec v[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) v[q] = *reinterpret_cast<const vec*>(src + at + (uint64_t)q * XB);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q)
+    __builtin_nontemporal_store(v[q] + (uint16_t)1, reinterpret_cast<vec*>(dst + at + (uint64_t)q * XB));
+}
+
 __global__ __launch_bounds__(256) void k_probe_copy4u(const float4* __restrict__ src, float4* __restrict__ dst,
                                                       uint64_t n) {
   const uint64_t base = blockIdx.x * 1024ull + threadIdx.x;
@@ -176,6 +195,21 @@ int plbm_probe_stream19s(const void* src, void* dst, uint32_t nodes, int nt, int
   if (!nt && order) hipLaunchKernelGGL((k_probe_stream19s<0, 1>), g, b, 0, st, s, d, nodes);
   if (nt && !order) hipLaunchKernelGGL((k_probe_stream19s<1, 0>), g, b, 0, st, s, d, nodes);
   if (nt && order) hipLaunchKernelGGL((k_probe_stream19s<1, 1>), g, b, 0, st, s, d, nodes);
+  return (int)hipGetLastError();
+}
+
+// 16-bit populations in blocks of 64 nodes, vec = 1, 2 or 4 nodes per thread;
+// nodes a multiple of 64; src and dst hold 19 * nodes 16-bit values each.
+int plbm_probe_stream19h(const void* src, void* dst, uint32_t nodes, int vec, void* stream) {
+  if (nodes == 0) return 0;
+  if ((vec != 1 && vec != 2 && vec != 4) || nodes % 64u) return (int)hipErrorInvalidValue;
+  const dim3 g((nodes / (uint32_t)vec + 255u) / 256u), b(256);
+  const hipStream_t st = (hipStream_t)stream;
+  const uint16_t* s = (const uint16_t*)src;
+  uint16_t* d = (uint16_t*)dst;
+  if (vec == 1) hipLaunchKernelGGL((k_probe_stream19h<1>), g, b, 0, st, s, d, nodes);
+  if (vec == 2) hipLaunchKernelGGL((k_probe_stream19h<2>), g, b, 0, st, s, d, nodes);
+  if (vec == 4) hipLaunchKernelGGL((k_probe_stream19h<4>), g, b, 0, st, s, d, nodes);
   return (int)hipGetLastError();
 }
 
