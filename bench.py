@@ -346,7 +346,7 @@ def precision_run(torch, N, Lattice, steps):
 CHANNELS = dict(width2d=(64, 512), width3d=(64, 192), channel_len=8, body_force=1e-6)
 
 
-def serve_run(N, seconds, budget_gb, collision="mrt", channel_frac=0.0):
+def serve_run(N, seconds, budget_gb, collision="mrt", channel_frac=0.0, split_nodes=()):
     """Continuous-batching serving of the Poisson request stream (50 req/s, 500 requests, seed 0): D2Q9 64^2 to
     1024^2 and D3Q19 64^3 to 192^3 droplets, T/Tc in [0.6, 0.9], radius [0.15, 0.35] of the side, f32, BGK or
     MRT, converged at max|du|/step <= 1e-8 over 100 steps; with channel_frac > 0 that share of the requests are
@@ -357,7 +357,7 @@ def serve_run(N, seconds, budget_gb, collision="mrt", channel_frac=0.0):
 
     def one(reqs, label):
         srv = Server(budget_bytes=int(budget_gb * 1e9), max_slots=64, max_tiles=1 << 21, check_every=100,
-                     tol=1e-8, max_steps=2_000_000, collision=collision)
+                     tol=1e-8, max_steps=2_000_000, collision=collision, split_nodes=split_nodes)
         last = [0.0]
 
         def progress(m):
@@ -375,11 +375,12 @@ def serve_run(N, seconds, budget_gb, collision="mrt", channel_frac=0.0):
     rate = max(0.8 * cap, 1e-3)
     second = one(from_synth(syn.request_stream(max(4, int(rate * seconds * 1.2)), rate, seed=1,
                                                channel_frac=channel_frac, **CHANNELS)), "sustainable")
-    return {"collision": collision, "channel_frac": channel_frac, "stream": first,
+    return {"collision": collision, "channel_frac": channel_frac, "split_nodes": list(split_nodes), "stream": first,
             "sustainable": dict(second, rate_per_s=rate)}
 
 
-def serving_leg(N, seconds=40.0, rate=0.5, seed=1, check_seconds=25.0, budget_gb=240.0, channel_frac=0.0):
+def serving_leg(N, seconds=40.0, rate=0.5, seed=1, check_seconds=25.0, budget_gb=240.0, channel_frac=0.0,
+                split_nodes=()):
     """Serving form at a sustainable rate, bounded: Poisson arrivals of the C5 mix for `seconds`, float32 MRT,
     converged at max|du|/step <= 1e-8 over 100 steps; then the cheapest converged requests solved again alone
     in float64 (within `check_seconds`) to state the served results' accuracy (droplet densities at the
@@ -390,7 +391,7 @@ def serving_leg(N, seconds=40.0, rate=0.5, seed=1, check_seconds=25.0, budget_gb
     reqs = from_synth(syn.request_stream(max(4, int(rate * seconds * 1.2)), rate, seed=seed,
                                          channel_frac=channel_frac, **CHANNELS))
     srv = Server(budget_bytes=int(budget_gb * 1e9), max_slots=64, max_tiles=1 << 21, check_every=100, tol=1e-8,
-                 max_steps=2_000_000, collision="mrt", record_results=True)
+                 max_steps=2_000_000, collision="mrt", record_results=True, split_nodes=split_nodes)
     out = srv.run(reqs, time_limit=seconds)
     srv.close()
     out.pop("records")
@@ -464,11 +465,15 @@ def main():
                     help="length of the bounded serving leg (0 skips it)")
     ap.add_argument("--serve-first", type=int, default=1,
                     help="1 (default): run the serving leg before the step benchmark; 0: after it")
+    ap.add_argument("--serve-split-nodes", default="262144",
+                    help="comma-separated node counts that split each lattice kind's serving lane by size "
+                         "(empty: one lane per kind)")
     ap.add_argument("--serve-channel-frac", type=float, default=0.0,
                     help="share of the served requests that are two-phase channels (width sweep) instead of droplets")
     ap.add_argument("--serve-collision", default="mrt", choices=["bgk", "mrt"],
                     help="collision of the served lattices (MRT: fewer unstable requests at low T/Tc)")
     args = ap.parse_args()
+    split = tuple(int(v) for v in args.serve_split_nodes.split(",") if v.strip())
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the lattice update is not sharded across GPUs here); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
@@ -497,13 +502,13 @@ def main():
     if args.serve:
         print(json.dumps({"metric": "solves/s + p50/p99 time to converged solution",
                           **serve_run(N, args.serve_seconds, args.serve_budget_gb, args.serve_collision,
-                                      args.serve_channel_frac)}),
+                                      args.serve_channel_frac, split)}),
               flush=True)
         return
     serving = None
 
     def run_serving_leg():
-        out = serving_leg(N, seconds=args.serve_leg_seconds, channel_frac=args.serve_channel_frac)
+        out = serving_leg(N, seconds=args.serve_leg_seconds, channel_frac=args.serve_channel_frac, split_nodes=split)
         log(f"[bench] serving leg: {out['converged']} converged, {out['solves_per_s']} solves/s, "
             f"p50 {out['latency_p50_s']} s, p99 {out['latency_p99_s']} s")
         torch.cuda.empty_cache()

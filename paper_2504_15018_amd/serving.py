@@ -178,7 +178,7 @@ def from_synth(reqs):
 
 
 class Lane:
-    """One batch of resident lattices of one lattice kind, on its own stream."""
+    """One batch of resident lattices of one lattice kind (and size class), on its own stream."""
 
     def __init__(self, torch, kind, max_slots, max_tiles):
         self.kind = kind
@@ -194,7 +194,7 @@ class Lane:
 
 
 class Server:
-    """Serving loop over one lane per lattice kind (D2Q9, D3Q19).
+    """Serving loop over one lane per lattice kind (D2Q9, D3Q19), or per kind and size class.
 
     Each lane is a batch on its own stream and advances at its own rate: a
     D2Q9 step of a few small lattices takes tens of microseconds, a D3Q19 step
@@ -203,12 +203,15 @@ class Server:
     enqueues `check_every` steps on every idle lane without waiting, then
     polls the lanes' completion events; a finished chunk is checked (residual,
     health) and the lane's queue is admitted while that lane is idle.  The HBM
-    budget is shared; each lane keeps arrival order in its own queue.
+    budget is shared; each lane keeps arrival order in its own queue.  With
+    `split_nodes` each kind is split further by lattice size, so that small
+    lattices, which need few steps, are not held to the step rate of the
+    largest lattice resident in their kind's lane.
     """
 
     def __init__(self, budget_bytes, max_slots=64, max_tiles=1 << 20, check_every=100, tol=1e-8,
                  max_steps=2_000_000, storage="f32", collision="bgk", keep_lattices=False, width=5.0,
-                 pattern="ab", record_results=False):
+                 pattern="ab", record_results=False, split_nodes=()):
         import torch
 
         self.torch = torch
@@ -224,6 +227,9 @@ class Server:
         self.keep = keep_lattices
         self.record_results = record_results
         self.width = width
+        # node-count thresholds that split each lattice kind into size classes with lanes of their own (a
+        # small lattice then advances at its class's pace, not at that of the largest lattice of its kind)
+        self.split_nodes = tuple(sorted(int(v) for v in split_nodes))
         self.lanes = {}
         self.used = 0
         self.peak_used = 0
@@ -236,10 +242,14 @@ class Server:
         lattice until then).  It ends with status "cancelled"."""
         self._cancel.add(rid)
 
-    def _lane(self, kind):
-        if kind not in self.lanes:
-            self.lanes[kind] = Lane(self.torch, kind, self.max_slots, self.max_tiles)
-        return self.lanes[kind]
+    def lane_key(self, req):
+        """(lattice kind, size class) of a request; the class counts the thresholds at or below its nodes."""
+        return (req.lattice, sum(req.nodes >= t for t in self.split_nodes))
+
+    def _lane(self, key):
+        if key not in self.lanes:
+            self.lanes[key] = Lane(self.torch, key, self.max_slots, self.max_tiles)
+        return self.lanes[key]
 
     @property
     def resident(self):
@@ -351,7 +361,7 @@ class Server:
                 if r.id in self._cancel:
                     r.status, r.done = "cancelled", now
                     continue
-                self._lane(r.lattice).queue.append(r)
+                self._lane(self.lane_key(r)).queue.append(r)
             progressed = False
             for lane in self.lanes.values():
                 if lane.inflight and lane.event.query():

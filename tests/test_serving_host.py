@@ -96,3 +96,16 @@ def test_unknown_problem_is_refused():
     import pytest
     with pytest.raises(ValueError):
         Request(0, 0.0, "D2Q9", (8, 8), 0.8, 2.0, problem="bubble")
+
+
+def test_lane_key_splits_kinds_by_size():
+    from paper_2504_15018_amd.serving import Server
+    srv = Server.__new__(Server)  # lane_key needs only the thresholds
+    srv.split_nodes = (262144,)
+    small = Request(0, 0.0, "D2Q9", (511, 511), 0.8, 2.0)
+    large = Request(1, 0.0, "D2Q9", (512, 512), 0.8, 2.0)
+    cube = Request(2, 0.0, "D3Q19", (64, 64, 64), 0.8, 2.0)
+    assert srv.lane_key(small) == ("D2Q9", 0) and srv.lane_key(large) == ("D2Q9", 1)
+    assert srv.lane_key(cube) == ("D3Q19", 1)
+    srv.split_nodes = ()
+    assert {srv.lane_key(r) for r in (small, large)} == {("D2Q9", 0)}
