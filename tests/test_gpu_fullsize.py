@@ -58,7 +58,8 @@ def _window_parity(lat, op, rho_fn, u0, dims, storage, steps, windows, out_size)
         err = rel_max(got, ref_in)
         fmt("window", lo=lo, rel_f=f"{err:.3e}")
         assert err <= tf, (lo, err)
-        rho_r, u_r = S.moments(op, ref)
+        with np.errstate(over="ignore", invalid="ignore"):  # the seams again
+            rho_r, u_r = S.moments(op, ref)
         rho_g = got.sum(axis=0)
         assert rel_max(rho_g, rho_r[inner]) <= tf
     return f_gpu
