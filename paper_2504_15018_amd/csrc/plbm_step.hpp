@@ -591,11 +591,12 @@ __global__ __launch_bounds__(NT, PLBM_MIN_WAVES) void k_step(const KParams* __re
   }
 
   // logical plane zl -> stored plane in [0, nz).  The march loads planes
-  // z0 - 1 <= zl <= z1 + 2 (one or two past the last plane the collision
-  // needs, whose values are never used: loading them unconditionally keeps
-  // the unrolled register rotation free of branches), and a periodic axis may
-  // be shorter than that window (nz = 1 or 2), so it wraps as often as
-  // needed; walls clamp.
+  // z0 - 1 <= zl <= z1 + n, n the planes it keeps in flight (one or two for
+  // the update, NM for the chemical-potential pass): up to n past the last
+  // plane the collision needs, whose values are never used (loading them
+  // unconditionally keeps the unrolled register rotation free of branches).
+  // A periodic axis may be shorter than that window (nz = 1, 2, ...), so it
+  // wraps as often as needed; walls clamp.
   auto wrapz = [&](int zl) {
     if constexpr (WALLS) {
       return zl < 0 ? 0 : (zl >= nz ? nz - 1 : zl);
