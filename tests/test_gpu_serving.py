@@ -194,3 +194,35 @@ def test_served_channels_and_droplets_match_solo_runs_and_the_fp64_method():
         assert ref["rho_in"] > 5 * ref["rho_out"]  # the droplet, or the liquid layer below the vapour, persists
     assert worst <= 1e-3
     srv.close()
+
+
+def test_size_class_lanes_keep_fifo_and_solo_results():
+    """With lanes split by lattice size, arrival order holds within each (kind, size class) lane, small and
+    large lattices of one kind advance on their own streams, and every result is still bitwise the same as
+    the request run alone."""
+    require_gpu()
+    import plbm_synth as syn
+    from paper_2504_15018_amd.serving import Server, from_synth, setup_lattice
+
+    fmt("serving_size_lanes")
+    reqs = from_synth(syn.request_stream(10, 200.0, seed=3, side2d=(24, 72), side3d=(12, 24), t_range=(0.75, 0.9)))
+    srv = Server(budget_bytes=1 << 34, max_slots=4, max_tiles=4096, check_every=50, tol=1e-6, max_steps=6000,
+                 keep_lattices=True, split_nodes=(2500,))
+    classes = {srv.lane_key(r) for r in reqs}
+    assert ("D2Q9", 0) in classes and ("D2Q9", 1) in classes  # both D2Q9 size classes occur
+    out = srv.run(reqs, time_limit=120)
+    print({k: v for k, v in out.items() if k != "records"}, flush=True)
+    assert out["unfinished"] == 0 and out["rejected"] == 0 and out["failed"] == 0
+    assert set(srv.lanes) == classes
+    for key in classes:
+        order = sorted((r for r in reqs if srv.lane_key(r) == key), key=lambda r: r.arrival)
+        admits = [r.admit for r in order]
+        assert admits == sorted(admits)
+    for r in reqs:
+        assert r.status in ("converged", "capped")
+        _, solo = setup_lattice(r, "f32", "bgk")
+        solo.step(r.steps)
+        assert np.array_equal(solo.populations(), r.lat.populations()), r.record()
+        solo.close()
+        r.lat.close()
+    srv.close()
