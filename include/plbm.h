@@ -108,7 +108,7 @@ extern "C" {
  * Per step: a chemical-potential pass (densities of the pulled populations,
  * mu of every node into one extra value per node, counted by
  * plbm_lattice_bytes), then the update.  Supported with the A-B pattern, F64
- * or F32 storage, mirror walls; not in a batch. */
+ * or F32 storage, mirror walls, alone or in a batch. */
 #define PLBM_SCHEME_WELL_BALANCED 1
 /* boundary kinds, per axis */
 #define PLBM_PERIODIC 0
@@ -321,10 +321,10 @@ int plbm_reduce_static(plbm_lattice* lat, plbm_diag* out);
 void plbm_destroy(plbm_lattice* lat);
 
 /* Continuous batching.  Attached lattices may differ in size, lattice kind,
- * collision, storage, pattern and walls; those that share all five ("a
- * type") are advanced by one launch per step (two for the in-place pattern)
- * whose workgroups cover the tiles of every such slot, so each step costs
- * one launch per type present.  max_slots
+ * collision, storage, pattern, walls and scheme; those that share all six ("a
+ * type") are advanced by one launch per step (two for the in-place pattern
+ * and for the well-balanced scheme) whose workgroups cover the tiles of every
+ * such slot, so each step costs one or two launches per type present.  max_slots
  * bounds the lattices attached at once and max_tiles their tiles together.
  * The batch owns no lattice memory; its work table lives in a caller-owned
  * device buffer of plbm_batch_bytes(max_slots, max_tiles) bytes and is

@@ -816,7 +816,7 @@ struct plbm_batch {
   char* red_dev;  // max_slots final reduction records
   std::vector<plbm_lattice*> lat;
   struct Group {
-    int lattice, coll, storage, walls, aa;
+    int lattice, coll, storage, walls, aa, wb;
     int offset, count;  // segment of the work table
   };
   std::vector<Group> groups;
@@ -858,7 +858,7 @@ int batch_rebuild(plbm_batch* b) {
   }
   b->groups.clear();
   b->work_host.clear();
-  std::map<std::tuple<int, int, int, int, int>, std::vector<int>> by_type;
+  std::map<std::tuple<int, int, int, int, int, int>, std::vector<int>> by_type;
   for (int s = 0; s < b->max_slots; ++s) {
     plbm_lattice* L = b->lat[s];
     if (!L) {
@@ -868,7 +868,8 @@ int batch_rebuild(plbm_batch* b) {
     KParams k = L->kp;
     k.parity = (int)(L->t & 1);
     b->slots_host[s] = k;
-    by_type[std::make_tuple(L->desc.lattice, L->desc.collision, L->desc.storage, L->kp.bb_z, L->kp.aa)].push_back(s);
+    by_type[std::make_tuple(L->desc.lattice, L->desc.collision, L->desc.storage, L->kp.bb_z, L->kp.aa, L->kp.wb)]
+        .push_back(s);
   }
   for (auto& kv : by_type) {
     plbm_batch::Group gr;
@@ -877,6 +878,7 @@ int batch_rebuild(plbm_batch* b) {
     gr.storage = std::get<2>(kv.first);
     gr.walls = std::get<3>(kv.first);
     gr.aa = std::get<4>(kv.first);
+    gr.wb = std::get<5>(kv.first);
     gr.offset = (int)b->work_host.size();
     for (int s : kv.second)
       for (int t = 0; t < b->lat[s]->lay.ntiles; ++t) b->work_host.push_back(WorkItem{s, t});
@@ -905,6 +907,7 @@ int batch_launch(plbm_batch* b, int mode, int phase) {
     a.mode = mode;
     a.walls = gr.walls;
     a.aa = gr.aa;
+    a.wb = gr.wb;
     a.psplit = psi_split(gr.storage);
     a.nblocks = gr.count;
     a.stream = b->stream;
@@ -956,7 +959,6 @@ int plbm_batch_create(int32_t max_slots, int64_t max_tiles, void* dev_mem, uint6
 
 int plbm_batch_attach(plbm_batch* b, plbm_lattice* L, int32_t* slot) {
   if (!b || !L || !slot) return set_error(PLBM_E_INVALID, "null argument");
-  if (L->kp.wb) return set_error(PLBM_E_UNSUPPORTED, "well-balanced lattices are not batched");
   if (L->batch) return set_error(PLBM_E_INVALID, "lattice already attached to a batch");
   for (int s = 0; s < b->max_slots; ++s) {
     if (!b->lat[s]) {

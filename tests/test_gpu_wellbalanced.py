@@ -12,7 +12,9 @@
    to round-off under the well-balanced scheme (float64), while the paper's
    discretisation of the same fluid keeps them; the settled droplet obeys
    Young-Laplace with the scheme's planar surface tension.
-4. Periodic marching axes of one to three planes (shorter than the planes
+4. In a batch beside a pseudopotential lattice, a well-balanced lattice steps
+   bitwise as it does alone.
+5. Periodic marching axes of one to three planes (shorter than the planes
    both launches load ahead) wrap inside an exact-size buffer.
 The fluid is the paper's EOS (R134a-like lattice densities 0.0375 / 1.187,
 interface width parameter xi = 3), gradient coefficient k = 0.15.
@@ -162,23 +164,51 @@ def test_spurious_currents_fall_to_round_off_and_laplace_holds():
     pp.close()
 
 
-def test_wb_lattices_are_not_batched():
+def test_wb_lattices_step_in_a_batch_like_alone():
+    """A well-balanced lattice and a pseudopotential one share a batch (separate launch groups, the
+    well-balanced group two launches per step): after batched steps, each lattice's populations and
+    reduction equal those of its solo twin, bitwise."""
     require_gpu()
     import torch
     from paper_2504_15018_amd import native as N
     from paper_2504_15018_amd.lattice import Lattice
-    fmt("wb_not_batched")
-    prm = N.plbm_params_paper_lattice(RV, RL, XI, 2.0, 1.0, 1.0, 1.0, [0.0, 0.0, 0.0])
-    lat = Lattice("D2Q9", (16, 16), prm, wb_k=K_GRAD)
-    nb = N.plbm_batch_bytes(2, 64)
-    mem = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
-    b = N.plbm_batch_create(2, 64, (mem.data_ptr() + 255) // 256 * 256, nb, lat.stream.cuda_stream)
-    with pytest.raises(N.PlbmError) as e:
-        N.plbm_batch_attach(b, lat.h)
-    assert e.value.code == N.PLBM_E_UNSUPPORTED
-    N.plbm_batch_destroy(b)
-    lat.close()
+    from gpu_cases import lib_params
+    fmt("wb_batched")
+    prm = N.plbm_params_paper_lattice(RV, RL, XI, 2.0, 1.0, 0.9, 1.1, [0.0, 0.0, 0.0])
+    stream = torch.cuda.Stream()
+    made = []
 
+    def make(kind, dims, params, **kw):
+        pair = []
+        for s in (stream, None):
+            lat = Lattice(kind, dims, params, collision="mrt", storage="f32", stream=s, **kw)
+            lat.init_shape(N.PLBM_SHAPE_DROPLET, params.rho_l, params.rho_v, W=6.0, R=min(dims) / 4.0)
+            pair.append(lat)
+        made.extend(pair)
+        return pair
+
+    wb_b, wb_s = make("D3Q19", (37, 21, 15), prm, wb_k=K_GRAD, wb_rho0=RV)
+    pp_b, pp_s = make("D2Q9", (70, 41), lib_params())
+    nb = N.plbm_batch_bytes(4, 4096)
+    mem = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    b = N.plbm_batch_create(4, 4096, (mem.data_ptr() + 255) // 256 * 256, nb, stream.cuda_stream)
+    for lat in (wb_b, pp_b):
+        lat.reduce()
+        N.plbm_batch_attach(b, lat.h)
+    N.plbm_batch_step(b, 37)
+    diag = N.plbm_batch_diag(b, 4)
+    stream.synchronize()
+    for solo in (wb_s, pp_s):
+        solo.reduce()
+        solo.step(37)
+    d_solo = [wb_s.reduce(), pp_s.reduce()]
+    for k, (bat, solo) in enumerate(((wb_b, wb_s), (pp_b, pp_s))):
+        assert np.array_equal(bat.populations(), solo.populations()), k
+        assert diag[k].mass == d_solo[k].mass and diag[k].max_u == d_solo[k].max_u, k
+        assert diag[k].flags == 0 and diag[k].time == 37
+    N.plbm_batch_destroy(b)
+    for lat in made:
+        lat.close()
 
 SHORT_AXES = [
     # lattice, dims (the last axis is the kernel's marching axis), steps
