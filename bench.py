@@ -530,7 +530,7 @@ def main():
     lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=6.0 if wb else 5.0, R=R, centre=[n / 2.0] * 3,
                    u0=(args.u0, 0.0, 0.0))
     stream = lat.stream
-    lat.step(0)  # captures the two-step replay graph now, outside the timed region
+    lat.step(0)  # captures the replay graphs now, outside the timed region
     log(f"[bench] lattice {dims} D3Q19 {args.collision} {args.storage} pattern {args.pattern}, "
         f"{lat.nbytes / 2**30:.2f} GiB; "
         f"warmup {args.warmup}")

@@ -276,7 +276,17 @@ int plbm_init_fields(plbm_lattice* lat, const double* rho, const double* u);
 /* f = f_eq of a density shape evaluated on the device; resets time to 0. */
 int plbm_init_shape(plbm_lattice* lat, const plbm_shape* shape);
 
-/* Enqueue n update steps on the lattice's stream; returns without waiting. */
+/* Enqueue n update steps on the lattice's stream and return without waiting.
+ * One step is the update of Sec. II for every node: the pull of eq. (LBE),
+ * density and momentum (eqs. Density, Momentum; u with F/2), psi (eq.
+ * Interaction_Potential, float64 radicand), the force stencil (eq.
+ * interactionForce), tau(rho) (Sec. VI), BGK or MRT collision with Guo forcing
+ * (eqs. Single_Phase_EDF, Guo_Forcing_Scheme) and the store (periodic, or
+ * half-way bounce-back walls on the last axis); or the well-balanced scheme of
+ * the descriptor.  The first call (n = 0 included) captures replay graphs of
+ * 16 and 2 steps; on a stream the caller is capturing, the launches go into
+ * the caller's graph.  Errors: PLBM_E_INVALID (n < 0, lattice attached to a
+ * batch), PLBM_E_DEVICE (a HIP error, its text in plbm_last_error). */
 int plbm_step(plbm_lattice* lat, int64_t n);
 
 /* rho[N] and u[d][N] at the current time (u includes F/2, eq. Momentum),
@@ -301,9 +311,13 @@ int plbm_write_populations(plbm_lattice* lat, const double* f);
 /* Steps taken since the last initialisation. */
 int plbm_get_time(plbm_lattice* lat, int64_t* t);
 
-/* Global diagnostics at the current time; stores u for the next residual.
- * Synchronises the stream.  Returns PLBM_E_UNSTABLE (with *out filled) when
- * the NaN or rho <= 0 flag is raised. */
+/* Global diagnostics at the current time (the moments of eqs. Density and
+ * Momentum, summed in a fixed order): compensated float64 mass, momentum,
+ * max|u|, the residual max|u(t) - u(t-k)|/k against the u stored by the
+ * previous reduction (k the steps since; u(t-k) kept in float32), and the
+ * health flags; stores u for the next residual.  Synchronises the stream.
+ * Returns PLBM_E_UNSTABLE (with *out filled) when the NaN or rho <= 0 flag is
+ * raised. */
 int plbm_reduce(plbm_lattice* lat, plbm_diag* out);
 
 /* plbm_reduce for callers that cannot allocate device memory or have none to
@@ -329,8 +343,8 @@ void plbm_destroy(plbm_lattice* lat);
  * The batch owns no lattice memory; its work table lives in a caller-owned
  * device buffer of plbm_batch_bytes(max_slots, max_tiles) bytes and is
  * rewritten on the first step after an attach or detach.  plbm_batch_step(n)
- * enqueues n steps of every attached lattice on the batch's stream (pairs of
- * steps replayed from a captured HIP graph).  Results are bitwise identical
+ * enqueues n steps of every attached lattice on the batch's stream (runs of
+ * 16 and 2 steps replayed from captured HIP graphs).  Results are bitwise identical
  * to stepping each lattice alone.  A lattice belongs to at most one batch at a
  * time: while attached, plbm_step, plbm_init_* and plbm_write_populations on
  * its own handle return PLBM_E_INVALID (reads stay allowed).  plbm_destroy of

@@ -271,6 +271,7 @@ struct plbm_lattice {
   int64_t t_red;
   bool has_red;
   hipGraphExec_t graph2;  // two steps (phase 0, phase 1)
+  hipGraphExec_t graphL;  // kLongSteps steps from phase 0
   bool has_graph;
   plbm_batch* batch;  // the batch the lattice is attached to, or null
   int32_t slot;
@@ -462,18 +463,41 @@ void fill_kparams(plbm_lattice* L) {
 
 int check_lat(plbm_lattice* L) { return L ? PLBM_OK : set_error(PLBM_E_INVALID, "null lattice"); }
 
-int capture_graph2(plbm_lattice* L) {
-  if (L->has_graph) return PLBM_OK;
+// Replay graphs: two steps, and kLongSteps steps (one graph launch carries
+// many kernels, so the gap the runtime leaves between consecutive graph
+// launches, about 8 us on MI355X, is paid once per kLongSteps steps).
+constexpr int kLongSteps = 16;
+
+// Capture `len` steps, phases 0, 1, 0, ..., issued by `launch(phase)` on
+// `stream`, into an executable graph.
+template <class F>
+int capture_steps(hipStream_t stream, int len, F&& launch, hipGraphExec_t* out) {
   hipGraph_t g;
-  HIPCHK(hipStreamBeginCapture(L->stream, hipStreamCaptureModeThreadLocal));
-  int st = run_step_kernel(L, MODE_STEP, 0, nullptr, nullptr);
-  if (st == PLBM_OK) st = run_step_kernel(L, MODE_STEP, 1, nullptr, nullptr);
-  hipError_t e = hipStreamEndCapture(L->stream, &g);
-  if (st != PLBM_OK) return st;
+  HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  int st = PLBM_OK;
+  for (int k = 0; k < len && st == PLBM_OK; ++k) st = launch(k & 1);
+  hipError_t e = hipStreamEndCapture(stream, &g);
+  if (st != PLBM_OK) {
+    if (e == hipSuccess) (void)hipGraphDestroy(g);
+    return st;
+  }
   if (e != hipSuccess) return set_error(PLBM_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
-  e = hipGraphInstantiate(&L->graph2, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return set_error(PLBM_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  return PLBM_OK;
+}
+
+int capture_graphs(plbm_lattice* L) {
+  if (L->has_graph) return PLBM_OK;
+  auto launch = [L](int phase) { return run_step_kernel(L, MODE_STEP, phase, nullptr, nullptr); };
+  int st = capture_steps(L->stream, 2, launch, &L->graph2);
+  if (st) return st;
+  st = capture_steps(L->stream, kLongSteps, launch, &L->graphL);
+  if (st) {
+    (void)hipGraphExecDestroy(L->graph2);
+    return st;
+  }
   L->has_graph = true;
   return PLBM_OK;
 }
@@ -595,16 +619,16 @@ int plbm_init_shape(plbm_lattice* L, const plbm_shape* s) {
 int plbm_step(plbm_lattice* L, int64_t n) {
   if (check_free(L)) return PLBM_E_INVALID;
   if (n < 0) return set_error(PLBM_E_INVALID, "negative step count");
-  // Step pairs replay a captured two-step graph.  It is captured on the
-  // first call (n = 0 included), so no later call pays for capture and
-  // instantiation.  The legacy null stream cannot be captured, and a stream
+  // Steps replay captured graphs of kLongSteps and two steps.  They are
+  // captured on the first call (n = 0 included), so no later call pays for
+  // capture and instantiation.  The legacy null stream cannot be captured, and a stream
   // the caller is capturing takes the launches directly into its own graph.
   bool replay = false;
   if (L->stream != nullptr && graphs_enabled()) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HIPCHK(hipStreamIsCapturing(L->stream, &cs));
     if (cs == hipStreamCaptureStatusNone) {
-      int st = capture_graph2(L);
+      int st = capture_graphs(L);
       if (st) return st;
       replay = true;
     }
@@ -616,6 +640,10 @@ int plbm_step(plbm_lattice* L, int64_t n) {
       if (st) return st;
       ++L->t;
       --n;
+    }
+    for (; n >= kLongSteps; n -= kLongSteps) {
+      HIPCHK(hipGraphLaunch(L->graphL, L->stream));
+      L->t += kLongSteps;
     }
     for (; n >= 2; n -= 2) {
       HIPCHK(hipGraphLaunch(L->graph2, L->stream));
@@ -797,7 +825,10 @@ int plbm_reduce_static(plbm_lattice* L, plbm_diag* out) {
 void plbm_destroy(plbm_lattice* L) {
   if (!L) return;
   if (L->batch) batch_forget(L->batch, L->slot);  // leaves the batch it was attached to
-  if (L->has_graph) (void)hipGraphExecDestroy(L->graph2);
+  if (L->has_graph) {
+    (void)hipGraphExecDestroy(L->graph2);
+    (void)hipGraphExecDestroy(L->graphL);
+  }
   delete L;
 }
 
@@ -824,7 +855,8 @@ struct plbm_batch {
   std::vector<WorkItem> work_host;
   int64_t g;  // steps since the last rebuild
   bool dirty;
-  hipGraphExec_t graph2;
+  hipGraphExec_t graph2;  // two steps (phase 0, phase 1)
+  hipGraphExec_t graphL;  // kLongSteps steps from phase 0
   bool has_graph;
 };
 
@@ -854,6 +886,7 @@ int batch_rebuild(plbm_batch* b) {
   if (!b->dirty) return PLBM_OK;
   if (b->has_graph) {
     (void)hipGraphExecDestroy(b->graph2);
+    (void)hipGraphExecDestroy(b->graphL);
     b->has_graph = false;
   }
   b->groups.clear();
@@ -991,16 +1024,14 @@ int plbm_batch_step(plbm_batch* b, int64_t n) {
   const int64_t n0 = n;
   if (n >= 4 && b->stream != nullptr && graphs_enabled()) {
     if (!b->has_graph) {
-      hipGraph_t gr;
-      HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-      int s1 = batch_launch(b, MODE_STEP, 0);
-      if (s1 == PLBM_OK) s1 = batch_launch(b, MODE_STEP, 1);
-      hipError_t e = hipStreamEndCapture(b->stream, &gr);
+      auto launch = [b](int phase) { return batch_launch(b, MODE_STEP, phase); };
+      int s1 = capture_steps(b->stream, 2, launch, &b->graph2);
       if (s1) return s1;
-      if (e != hipSuccess) return set_error(PLBM_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
-      e = hipGraphInstantiate(&b->graph2, gr, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(gr);
-      if (e != hipSuccess) return set_error(PLBM_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      s1 = capture_steps(b->stream, kLongSteps, launch, &b->graphL);
+      if (s1) {
+        (void)hipGraphExecDestroy(b->graph2);
+        return s1;
+      }
       b->has_graph = true;
     }
     if (b->g & 1) {
@@ -1008,6 +1039,10 @@ int plbm_batch_step(plbm_batch* b, int64_t n) {
       if (st) return st;
       ++b->g;
       --n;
+    }
+    for (; n >= kLongSteps; n -= kLongSteps) {
+      HIPCHK(hipGraphLaunch(b->graphL, b->stream));
+      b->g += kLongSteps;
     }
     for (; n >= 2; n -= 2) {
       HIPCHK(hipGraphLaunch(b->graph2, b->stream));
@@ -1048,7 +1083,10 @@ void plbm_batch_destroy(plbm_batch* b) {
       b->lat[s]->batch = nullptr;
       b->lat[s]->slot = -1;
     }
-  if (b->has_graph) (void)hipGraphExecDestroy(b->graph2);
+  if (b->has_graph) {
+    (void)hipGraphExecDestroy(b->graph2);
+    (void)hipGraphExecDestroy(b->graphL);
+  }
   delete b;
 }
 
