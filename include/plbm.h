@@ -334,7 +334,10 @@ int plbm_reduce_static(plbm_lattice* lat, plbm_diag* out);
 /* Release the handle (not the caller's device memory). */
 void plbm_destroy(plbm_lattice* lat);
 
-/* Continuous batching.  Attached lattices may differ in size, lattice kind,
+/* Continuous batching (a serving form; the paper has none): a batch step is
+ * the update of plbm_step (Sec. II) for every attached lattice, and
+ * plbm_batch_diag the reduction of plbm_reduce for each.  Attached lattices
+ * may differ in size, lattice kind,
  * collision, storage, pattern, walls and scheme; those that share all six ("a
  * type") are advanced by one launch per step (two for the in-place pattern
  * and for the well-balanced scheme) whose workgroups cover the tiles of every
