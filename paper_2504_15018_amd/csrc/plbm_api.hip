@@ -271,7 +271,7 @@ struct plbm_lattice {
   int64_t t_red;
   bool has_red;
   hipGraphExec_t graph2;  // two steps (phase 0, phase 1)
-  hipGraphExec_t graphL;  // kLongSteps steps from phase 0
+  hipGraphExec_t graphL;  // long_steps() steps from phase 0
   bool has_graph;
   plbm_batch* batch;  // the batch the lattice is attached to, or null
   int32_t slot;
@@ -353,11 +353,25 @@ int psi_split(int storage) {
   return storage_bytes(storage) == 2 ? 8 : 1;
 }
 
-// Multi-step calls replay captured two-step graphs unless PLBM_NO_GRAPH is set
-// (read once).
+// Multi-step calls replay captured graphs unless PLBM_NO_GRAPH is set (read
+// once).
 bool graphs_enabled() {
   static const bool on = std::getenv("PLBM_NO_GRAPH") == nullptr;
   return on;
+}
+
+// Steps of the long replay graph (one graph launch carries many kernels, so
+// the gap the runtime leaves between consecutive graph launches, about 8 us on
+// MI355X, is paid once per that many steps); PLBM_LONG_GRAPH overrides (an
+// even count >= 4; 0: two-step graphs only), read once.
+int long_steps() {
+  static const int n = [] {
+    const char* e = std::getenv("PLBM_LONG_GRAPH");
+    if (!e) return 16;
+    const int v = std::atoi(e);
+    return (v >= 4 && v % 2 == 0) ? v : 0;
+  }();
+  return n;
 }
 
 int run_step_kernel(plbm_lattice* L, int mode, int phase, double* orho, double* ou, void* red = nullptr) {
@@ -463,11 +477,6 @@ void fill_kparams(plbm_lattice* L) {
 
 int check_lat(plbm_lattice* L) { return L ? PLBM_OK : set_error(PLBM_E_INVALID, "null lattice"); }
 
-// Replay graphs: two steps, and kLongSteps steps (one graph launch carries
-// many kernels, so the gap the runtime leaves between consecutive graph
-// launches, about 8 us on MI355X, is paid once per kLongSteps steps).
-constexpr int kLongSteps = 16;
-
 // Capture `len` steps, phases 0, 1, 0, ..., issued by `launch(phase)` on
 // `stream`, into an executable graph.
 template <class F>
@@ -493,10 +502,12 @@ int capture_graphs(plbm_lattice* L) {
   auto launch = [L](int phase) { return run_step_kernel(L, MODE_STEP, phase, nullptr, nullptr); };
   int st = capture_steps(L->stream, 2, launch, &L->graph2);
   if (st) return st;
-  st = capture_steps(L->stream, kLongSteps, launch, &L->graphL);
-  if (st) {
-    (void)hipGraphExecDestroy(L->graph2);
-    return st;
+  if (long_steps() > 0) {
+    st = capture_steps(L->stream, long_steps(), launch, &L->graphL);
+    if (st) {
+      (void)hipGraphExecDestroy(L->graph2);
+      return st;
+    }
   }
   L->has_graph = true;
   return PLBM_OK;
@@ -619,7 +630,7 @@ int plbm_init_shape(plbm_lattice* L, const plbm_shape* s) {
 int plbm_step(plbm_lattice* L, int64_t n) {
   if (check_free(L)) return PLBM_E_INVALID;
   if (n < 0) return set_error(PLBM_E_INVALID, "negative step count");
-  // Steps replay captured graphs of kLongSteps and two steps.  They are
+  // Steps replay captured graphs of long_steps() and two steps.  They are
   // captured on the first call (n = 0 included), so no later call pays for
   // capture and instantiation.  The legacy null stream cannot be captured, and a stream
   // the caller is capturing takes the launches directly into its own graph.
@@ -641,9 +652,9 @@ int plbm_step(plbm_lattice* L, int64_t n) {
       ++L->t;
       --n;
     }
-    for (; n >= kLongSteps; n -= kLongSteps) {
+    for (const int m = long_steps(); m > 0 && n >= m; n -= m) {
       HIPCHK(hipGraphLaunch(L->graphL, L->stream));
-      L->t += kLongSteps;
+      L->t += m;
     }
     for (; n >= 2; n -= 2) {
       HIPCHK(hipGraphLaunch(L->graph2, L->stream));
@@ -827,7 +838,7 @@ void plbm_destroy(plbm_lattice* L) {
   if (L->batch) batch_forget(L->batch, L->slot);  // leaves the batch it was attached to
   if (L->has_graph) {
     (void)hipGraphExecDestroy(L->graph2);
-    (void)hipGraphExecDestroy(L->graphL);
+    if (long_steps() > 0) (void)hipGraphExecDestroy(L->graphL);
   }
   delete L;
 }
@@ -856,7 +867,7 @@ struct plbm_batch {
   int64_t g;  // steps since the last rebuild
   bool dirty;
   hipGraphExec_t graph2;  // two steps (phase 0, phase 1)
-  hipGraphExec_t graphL;  // kLongSteps steps from phase 0
+  hipGraphExec_t graphL;  // long_steps() steps from phase 0
   bool has_graph;
 };
 
@@ -886,7 +897,7 @@ int batch_rebuild(plbm_batch* b) {
   if (!b->dirty) return PLBM_OK;
   if (b->has_graph) {
     (void)hipGraphExecDestroy(b->graph2);
-    (void)hipGraphExecDestroy(b->graphL);
+    if (long_steps() > 0) (void)hipGraphExecDestroy(b->graphL);
     b->has_graph = false;
   }
   b->groups.clear();
@@ -1027,10 +1038,12 @@ int plbm_batch_step(plbm_batch* b, int64_t n) {
       auto launch = [b](int phase) { return batch_launch(b, MODE_STEP, phase); };
       int s1 = capture_steps(b->stream, 2, launch, &b->graph2);
       if (s1) return s1;
-      s1 = capture_steps(b->stream, kLongSteps, launch, &b->graphL);
-      if (s1) {
-        (void)hipGraphExecDestroy(b->graph2);
-        return s1;
+      if (long_steps() > 0) {
+        s1 = capture_steps(b->stream, long_steps(), launch, &b->graphL);
+        if (s1) {
+          (void)hipGraphExecDestroy(b->graph2);
+          return s1;
+        }
       }
       b->has_graph = true;
     }
@@ -1040,9 +1053,9 @@ int plbm_batch_step(plbm_batch* b, int64_t n) {
       ++b->g;
       --n;
     }
-    for (; n >= kLongSteps; n -= kLongSteps) {
+    for (const int m = long_steps(); m > 0 && n >= m; n -= m) {
       HIPCHK(hipGraphLaunch(b->graphL, b->stream));
-      b->g += kLongSteps;
+      b->g += m;
     }
     for (; n >= 2; n -= 2) {
       HIPCHK(hipGraphLaunch(b->graph2, b->stream));
@@ -1085,7 +1098,7 @@ void plbm_batch_destroy(plbm_batch* b) {
     }
   if (b->has_graph) {
     (void)hipGraphExecDestroy(b->graph2);
-    (void)hipGraphExecDestroy(b->graphL);
+    if (long_steps() > 0) (void)hipGraphExecDestroy(b->graphL);
   }
   delete b;
 }
