@@ -1,4 +1,5 @@
-"""Host replay of the z march of the fused A-B update kernel (k_step).
+"""Host replay of the z marches of the fused A-B update kernel (k_step) and of
+the in-place update (k_aa_step, whose psi ring is loaded a plane ahead).
 
 The kernel's tile waves and halo waves walk a chunk [z0, z1) of z planes
 with one barrier per collided plane, loading each plane's populations ahead
@@ -196,3 +197,46 @@ def test_short_periodic_axis_wraps_inside_the_array():
         for zl in range(-1, nz + 6):
             p = wrapz(zl, nz, False)
             assert 0 <= p < nz and (p - zl) % nz == 0
+
+
+def inplace_march(tr):
+    """The in-place update's z march: psi of ring plane zl is loaded into a register set (issue) a plane
+    iteration before it is written to its LDS slot (commit); iteration z commits plane z+1, issues the psi of
+    plane z+2, loads the populations of plane z+1, passes the plane barrier and updates plane z."""
+    z0, z1 = tr.z0, tr.z1
+    tr.issue(z0 - 1, "pa"); tr.finish(z0 - 1, "pa", "t")
+    tr.issue(z0, "pa"); tr.finish(z0, "pa", "t")
+    tr.issue(z0 + 1, "pa")
+    tr.issue(z0, "va")  # populations of plane z0
+
+    def plane_step(z, cur, nxt, pc, pn):
+        tr.finish(z + 1, pc, "t")
+        tr.issue(z + 2, pn)
+        if z + 1 < z1:
+            tr.issue(z + 1, nxt)
+        tr.barrier()
+        tr.collide(z, cur)
+
+    z = z0
+    while z + 1 < z1:
+        plane_step(z, "va", "vb", "pa", "pb")
+        plane_step(z + 1, "vb", "va", "pb", "pa")
+        z += 2
+    if z < z1:
+        plane_step(z, "va", "vb", "pa", "pb")
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_inplace_march_stays_in_bounds_and_race_free(walls):
+    for nz in range(1, 10):
+        for cz in range(1, nz + 1):
+            for z0, z1 in chunks(nz, cz):
+                tr = Trace(nz, walls, z0, z1)
+                inplace_march(tr)
+                assert tr.interval == z1 - z0
+                assert sorted({r[2] for r in tr.reads}) == list(range(z0 - 1, z1 + 1))
+                assert max(tr.loaded) <= z1 + 1  # the psi of one plane past the last one the update reads
+                for k, slot, zz in tr.reads:
+                    assert not any(w[0] == k and w[1] == slot for w in tr.writes), (nz, cz, z0, k, slot)
+                    prior = [w for w in tr.writes if w[1] == slot and w[0] < k]
+                    assert prior and prior[-1][2] == zz, (nz, cz, z0, k, slot, zz, prior[-1:])
