@@ -16,6 +16,11 @@
 // plain (NT = 0) or non-temporal stores, all loads before the stores
 // (ORDER = 0) or each direction stored right after its load (ORDER = 1).
 // k_probe_copy4nt: the float4 copy with non-temporal stores.
+// k_probe_read19<ORDER>: the 19 arrays read once, their sum written once per
+// node (a read-mostly pass), on a cube of side 256: ORDER 0 one node per
+// thread in memory order; ORDER 1 a 64 x 8 tile of one plane per workgroup
+// (the tiles of a plane consecutive); ORDER 2 a 64 x 8 tile column per
+// workgroup marching through 256 / SPLIT planes (SPLIT chunks per column).
 // k_probe_stream19h<V>: 19 arrays of 16-bit values in blocks of 64 nodes (128
 // bytes per direction), V = 1, 2 or 4 consecutive nodes per thread (2-, 4- or
 // 8-byte accesses), non-temporal stores: the 16-bit update's bytes.
@@ -116,6 +121,31 @@ __global__ __launch_bounds__(256) void k_probe_stream19h(const uint16_t* __restr
     __builtin_nontemporal_store(v[q] + (uint16_t)1, reinterpret_cast<vec*>(dst + at + (uint64_t)q * XB));
 }
 
+template <int ORDER, int SPLIT>
+__global__ __launch_bounds__(512) void k_probe_read19(const float* __restrict__ src, float* __restrict__ dst) {
+  constexpr uint32_t S = 256;  // cube side
+  auto node = [&](uint32_t n) {
+    const uint64_t at = (uint64_t)(n / kXB) * (kQ * kXB) + (n % kXB);
+    float r = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) r += src[at + (uint64_t)q * kXB];
+    __builtin_nontemporal_store(r, dst + n);
+  };
+  const uint32_t t = threadIdx.x;
+  if constexpr (ORDER == 0) {
+    node(blockIdx.x * 512u + t);
+  } else {
+    const uint32_t tile = blockIdx.x % 128u;  // 4 x 32 tiles of 64 x 8 per plane
+    const uint32_t x = (tile % 4u) * 64u + t % 64u, y = (tile / 4u) * 8u + t / 64u;
+    if constexpr (ORDER == 1) {
+      node((blockIdx.x / 128u * S + y) * S + x);
+    } else {
+      const uint32_t z0 = blockIdx.x / 128u * (S / SPLIT);
+      for (uint32_t z = z0; z < z0 + S / SPLIT; ++z) node((z * S + y) * S + x);
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_probe_copy4u(const float4* __restrict__ src, float4* __restrict__ dst,
                                                       uint64_t n) {
   const uint64_t base = blockIdx.x * 1024ull + threadIdx.x;
@@ -210,6 +240,21 @@ int plbm_probe_stream19h(const void* src, void* dst, uint32_t nodes, int vec, vo
   if (vec == 1) hipLaunchKernelGGL((k_probe_stream19h<1>), g, b, 0, st, s, d, nodes);
   if (vec == 2) hipLaunchKernelGGL((k_probe_stream19h<2>), g, b, 0, st, s, d, nodes);
   if (vec == 4) hipLaunchKernelGGL((k_probe_stream19h<4>), g, b, 0, st, s, d, nodes);
+  return (int)hipGetLastError();
+}
+
+// Read-mostly pass over a 256^3 cube (src: 19 * 256^3 floats, dst: 256^3
+// floats); order 0, 1 as k_probe_read19, 2 and 3 its tile columns in 2 and 16
+// chunks.
+int plbm_probe_read19(const void* src, void* dst, int order, void* stream) {
+  const hipStream_t st = (hipStream_t)stream;
+  const float* s = (const float*)src;
+  float* d = (float*)dst;
+  if (order == 0) hipLaunchKernelGGL((k_probe_read19<0, 1>), dim3(256u * 256u * 256u / 512u), dim3(512), 0, st, s, d);
+  else if (order == 1) hipLaunchKernelGGL((k_probe_read19<1, 1>), dim3(128u * 256u), dim3(512), 0, st, s, d);
+  else if (order == 2) hipLaunchKernelGGL((k_probe_read19<2, 2>), dim3(128u * 2u), dim3(512), 0, st, s, d);
+  else if (order == 3) hipLaunchKernelGGL((k_probe_read19<2, 16>), dim3(128u * 16u), dim3(512), 0, st, s, d);
+  else return (int)hipErrorInvalidValue;
   return (int)hipGetLastError();
 }
 
