@@ -224,6 +224,8 @@ def stream_probe(torch, nodes=256 ** 3, reps=50):
                                          ctypes.c_void_p]
     lib.plbm_probe_stream19h.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int,
                                          ctypes.c_void_p]
+    lib.plbm_probe_pingpong.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_void_p]
     lib.plbm_probe_read19.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
     lib.plbm_probe_copy4nt.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
     lib.plbm_probe_stream19x.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
@@ -244,6 +246,14 @@ def stream_probe(torch, nodes=256 ** 3, reps=50):
              lambda: lib.plbm_probe_stream19s(a.data_ptr(), b.data_ptr(), nodes, 0, 1, sp)),
             ("stream19_interleaved", lambda: lib.plbm_probe_stream19s(a.data_ptr(), b.data_ptr(), nodes, 1, 1, sp)),
             ("copy4", lambda: lib.plbm_probe_copy4(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp)),
+            # ping-pong pairs (two passes per call; rates of both passes' bytes): the second pass in the first's
+            # order, or reversed so that it starts on the blocks the first wrote last
+            ("pingpong_same_order", lambda: lib.plbm_probe_pingpong(a.data_ptr(), b.data_ptr(), nodes, 1, 0, sp)),
+            ("pingpong_reversed", lambda: lib.plbm_probe_pingpong(a.data_ptr(), b.data_ptr(), nodes, 1, 1, sp)),
+            ("pingpong_plain_stores_same_order",
+             lambda: lib.plbm_probe_pingpong(a.data_ptr(), b.data_ptr(), nodes, 0, 0, sp)),
+            ("pingpong_plain_stores_reversed",
+             lambda: lib.plbm_probe_pingpong(a.data_ptr(), b.data_ptr(), nodes, 0, 1, sp)),
             # read-mostly passes (19 values read, one written per node); rates of those bytes
             ("read19_linear", lambda: lib.plbm_probe_read19(a.data_ptr(), b.data_ptr(), 0, sp)),
             ("read19_tiles_per_plane", lambda: lib.plbm_probe_read19(a.data_ptr(), b.data_ptr(), 1, sp)),
@@ -261,6 +271,8 @@ def stream_probe(torch, nodes=256 ** 3, reps=50):
         t = timed(fn)
         out[name + "_us"] = round(t * 1e6, 1)
         nbytes = moved // 2 if name.startswith("half_") else (20 * 4 * nodes if name.startswith("read19") else moved)
+        if name.startswith("pingpong"):
+            nbytes = 2 * moved
         out[name + "_GBps"] = round(nbytes / t / 1e9, 1)
     return out
 

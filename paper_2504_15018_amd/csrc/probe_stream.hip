@@ -24,6 +24,10 @@
 // k_probe_stream19h<V>: 19 arrays of 16-bit values in blocks of 64 nodes (128
 // bytes per direction), V = 1, 2 or 4 consecutive nodes per thread (2-, 4- or
 // 8-byte accesses), non-temporal stores: the 16-bit update's bytes.
+// k_probe_pingpong<NT>: the 19-array stream of k_probe_stream19 (NT = 1) or
+// with plain stores (NT = 0), its workgroups taking the blocks in memory order
+// or (rev) in reverse, for ping-pong pairs (a to b, then b to a) in which the
+// second pass starts where the first ended.
 // k_probe_copy4: a plain float4 copy, one vector per thread;
 // k_probe_copy4u: the same with four vectors per thread (a block-stride loop).
 #include <hip/hip_runtime.h>
@@ -44,6 +48,23 @@ __global__ __launch_bounds__(256) void k_probe_stream19(const float* __restrict_
   for (int q = 0; q < kQ; ++q) v[q] = src[at + (uint64_t)q * kXB];
 #pragma unroll
   for (int q = 0; q < kQ; ++q) __builtin_nontemporal_store(v[q] + 1.0f, dst + at + (uint64_t)q * kXB);
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_probe_pingpong(const float* __restrict__ src, float* __restrict__ dst,
+                                                        uint32_t nodes, int rev) {
+  const uint32_t blk = rev ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
+  const uint32_t n = blk * 256u + threadIdx.x;
+  if (n >= nodes) return;
+  const uint64_t at = (uint64_t)(n / kXB) * (kQ * kXB) + (n % kXB);
+  float v[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) v[q] = src[at + (uint64_t)q * kXB];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    if constexpr (NT) __builtin_nontemporal_store(v[q] + 1.0f, dst + at + (uint64_t)q * kXB);
+    else dst[at + (uint64_t)q * kXB] = v[q] + 1.0f;
+  }
 }
 
 template <int V>
@@ -173,6 +194,23 @@ __global__ __launch_bounds__(256) void k_probe_copy4(const float4* __restrict__ 
 extern "C" {
 
 // src and dst hold 19 * 32 * ceil(nodes / 32) floats each; returns a hipError_t.
+// A ping-pong pair over 19 arrays of `nodes` floats in the blocked layout: a
+// to b in memory order, then b to a in memory order (alternate = 0) or in
+// reverse (alternate = 1); nt selects non-temporal stores.
+int plbm_probe_pingpong(void* a, void* b, uint32_t nodes, int nt, int alternate, void* stream) {
+  if (nodes == 0) return 0;
+  const hipStream_t st = (hipStream_t)stream;
+  const dim3 grid((nodes + 255u) / 256u);
+  if (nt) {
+    hipLaunchKernelGGL((k_probe_pingpong<1>), grid, dim3(256), 0, st, (const float*)a, (float*)b, nodes, 0);
+    hipLaunchKernelGGL((k_probe_pingpong<1>), grid, dim3(256), 0, st, (const float*)b, (float*)a, nodes, alternate);
+  } else {
+    hipLaunchKernelGGL((k_probe_pingpong<0>), grid, dim3(256), 0, st, (const float*)a, (float*)b, nodes, 0);
+    hipLaunchKernelGGL((k_probe_pingpong<0>), grid, dim3(256), 0, st, (const float*)b, (float*)a, nodes, alternate);
+  }
+  return (int)hipGetLastError();
+}
+
 int plbm_probe_stream19(const void* src, void* dst, uint32_t nodes, void* stream) {
   if (nodes == 0) return 0;
   hipLaunchKernelGGL(k_probe_stream19, dim3((nodes + 255u) / 256u), dim3(256), 0, (hipStream_t)stream,
