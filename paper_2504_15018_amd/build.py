@@ -40,8 +40,10 @@ SOURCES = {
     # 64 x 4 tiles in 16-bit storage: three workgroups of four waves per CU
     # instead of one of eight hide the latency of these instruction-bound
     # formats (256^3 step 0.787 -> 0.640 ms in f16r, 0.660 -> 0.540 in bf16s;
-    # 64 x 12 and 32 x 4 were slower); float32 stays fastest at 64 x 8.
-    "plbm_k_f64.hip": ["-ffp-contract=off", "-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=4"],
+    # 64 x 12 and 32 x 4 were slower); float32 stays fastest at 64 x 8, and so
+    # does float64 (two workgroups of four waves at 220 registers; 256^3 step
+    # 1.665 -> 1.559 ms; 32 x 8 1.700).
+    "plbm_k_f64.hip": ["-ffp-contract=off", "-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=4", "-DPLBM_AA_TY=8"],
     "plbm_k_f32.hip": ["-DPLBM_PREFETCH=1", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3"],
     "plbm_k_f16s.hip": ["-DPLBM_PREFETCH=2", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3", "-DPLBM_AA_TY=4"],
     "plbm_k_bf16s.hip": ["-DPLBM_PREFETCH=2", "-DPLBM_D3_TX=64", "-DPLBM_D3_TY=8", "-DPLBM_MIN_WAVES=3", "-DPLBM_AA_TY=4"],
