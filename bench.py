@@ -226,6 +226,8 @@ def stream_probe(torch, nodes=256 ** 3, reps=50):
                                          ctypes.c_void_p]
     lib.plbm_probe_pingpong.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_void_p]
+    lib.plbm_probe_stream19_lds.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                            ctypes.c_void_p]
     lib.plbm_probe_read19.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
     lib.plbm_probe_copy4nt.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
     lib.plbm_probe_stream19x.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
@@ -246,6 +248,10 @@ def stream_probe(torch, nodes=256 ** 3, reps=50):
              lambda: lib.plbm_probe_stream19s(a.data_ptr(), b.data_ptr(), nodes, 0, 1, sp)),
             ("stream19_interleaved", lambda: lib.plbm_probe_stream19s(a.data_ptr(), b.data_ptr(), nodes, 1, 1, sp)),
             ("copy4", lambda: lib.plbm_probe_copy4(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp)),
+            # the one-node stream with its workgroups per CU capped by unused LDS (8, 5, 4, 3, 2 of 160 KiB)
+            *[(f"stream19_lds_{k}k", (lambda k=k: lib.plbm_probe_stream19_lds(a.data_ptr(), b.data_ptr(), nodes,
+                                                                               k * 1024, sp)))
+              for k in (20, 32, 40, 53, 64)],
             # ping-pong pairs (two passes per call; rates of both passes' bytes): the second pass in the first's
             # order, or reversed so that it starts on the blocks the first wrote last
             ("pingpong_same_order", lambda: lib.plbm_probe_pingpong(a.data_ptr(), b.data_ptr(), nodes, 1, 0, sp)),

@@ -211,6 +211,17 @@ int plbm_probe_pingpong(void* a, void* b, uint32_t nodes, int nt, int alternate,
   return (int)hipGetLastError();
 }
 
+// plbm_probe_stream19 with `lds` bytes of dynamic LDS per workgroup (unused),
+// which caps the workgroups resident per CU (160 KiB of LDS per CU) and so
+// the loads in flight; lds at most 65536.
+int plbm_probe_stream19_lds(const void* src, void* dst, uint32_t nodes, uint32_t lds, void* stream) {
+  if (nodes == 0) return 0;
+  if (lds > 65536u) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_probe_stream19, dim3((nodes + 255u) / 256u), dim3(256), lds, (hipStream_t)stream,
+                     (const float*)src, (float*)dst, nodes);
+  return (int)hipGetLastError();
+}
+
 int plbm_probe_stream19(const void* src, void* dst, uint32_t nodes, void* stream) {
   if (nodes == 0) return 0;
   hipLaunchKernelGGL(k_probe_stream19, dim3((nodes + 255u) / 256u), dim3(256), 0, (hipStream_t)stream,
