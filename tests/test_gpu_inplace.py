@@ -100,8 +100,9 @@ def test_inplace_equals_ab_bitwise(spec):
         r2, u2 = aa.moments()
         assert np.array_equal(r1, r2) and np.array_equal(u1, u2)
         d1, d2 = ab.reduce(), aa.reduce()
-        # the patterns may tile differently (16-bit storage: 64 x 4 in place, 64 x 8 in A-B), which regroups
-        # the per-tile partial sums: mass and momentum agree to rounding, the maximum exactly
+        # the patterns may tile differently (16-bit storage: 64 x 4 in place, 64 x 8 in A-B; float64 the
+        # reverse), which regroups the per-tile partial sums: mass and momentum agree to rounding, the maximum
+        # exactly
         assert d1.mass == pytest.approx(d2.mass, rel=4e-16 * 8)
         scale = d1.mass * max(d1.max_u, 1e-30)
         assert np.allclose(list(d1.momentum), list(d2.momentum), rtol=0, atol=1e-14 * scale)
