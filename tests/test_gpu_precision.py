@@ -93,14 +93,20 @@ def test_roundtrip_local_and_global_shift(storage):
 
 # Bars against float64 after 40 000 steps of the channel: bulk liquid and
 # vapour densities (relative) and the velocity profile (max|du_x| / max|u_x|).
-# Unshifted float32 stores whole populations, so its rounding walks the
-# density by ~6e-8 sqrt(steps); the locally shifted formats meet the 1e-3
-# coexistence bar and float16 also resolves the profile; the globally shifted
-# formats hold the liquid only (the vapour, 30 times lighter, sits far from the
-# single reference density) and do not resolve a 1e-6 body force at all.
+# Unshifted float32 conserves each node's mass in the collision up to one
+# rounding of the rest population, so its densities stay within a few 1e-7
+# (3.9e-7 / 2.5e-7 measured; 2.0e-5 / 2.6e-5 while the rest population took
+# the rounding of the density sum every step); the locally shifted formats
+# meet the 1e-3 coexistence bar and float16 also resolves the profile, to a
+# few 1e-3 (3.1e-3 and 1.1e-2 on the two rounding paths of the rest
+# population: a 1e-6 body force moves each population by less than its
+# resolution, so the profile error depends on how the roundings fall); the
+# globally shifted formats hold the liquid only (the vapour, 30 times lighter,
+# sits far from the single reference density) and do not resolve a 1e-6 body
+# force at all.
 BARS = {
-    "f32": (5e-5, 5e-5, 1e-2),
-    "f16r": (1e-3, 1e-3, 1e-2),
+    "f32": (2e-6, 2e-6, 5e-3),
+    "f16r": (1e-3, 1e-3, 2e-2),
     "bf16r": (1e-3, 1e-3, 0.2),
     "f16s": (1e-3, 0.2, None),
     "bf16s": (1e-3, 0.2, None),

@@ -16,6 +16,8 @@
    bitwise as it does alone.
 5. Periodic marching axes of one to three planes (shorter than the planes
    both launches load ahead) wrap inside an exact-size buffer.
+6. The benchmark's 256^3 workload, float32 and float64: sampled windows
+   against the oracle on light-cone-padded boxes.
 The fluid is the paper's EOS (R134a-like lattice densities 0.0375 / 1.187,
 interface width parameter xi = 3), gradient coefficient k = 0.15.
 """
@@ -269,3 +271,56 @@ def test_wb_short_periodic_marching_axis_stays_inside_the_lattice(case, storage)
     finally:
         stream.synchronize()
         N.plbm_destroy(h)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_wb_droplet_256cubed_mrt_windows(storage):
+    """The benchmark's well-balanced workload at full size: D3Q19 256^3, MRT, the paper's EOS with k = 0.15,
+    droplet R = 48 (tanh width 2 xi), stepped 8 times through the replay graphs.  The update at a node reads
+    populations one node away, the chemical potential one node further and the density one beyond that, so
+    after K steps a node depends on the initial state within 3K nodes, and its moments (the force's chemical
+    potential) within 3K + 2: windows of 8^3 nodes (interface, centre, a corner wrapped across three faces,
+    vapour) must match the oracle run on periodic boxes with a 3K + 2 margin."""
+    require_gpu()
+    fmt("wb_fullsize", storage=storage)
+    dims, steps, out = (256, 256, 256), 8, 8
+    wb = _oracle("D3Q19", "mrt", False, 1.0, 1.0)
+    lat = _lattice("D3Q19", dims, "mrt", storage, False, 1.0, 1.0)
+
+    def rho_fn(co):
+        return syn.droplet(co, dims, RV, RL, R=48.0, W=2 * XI)
+
+    lat.init_fields(rho_fn(syn.grid(dims)))
+    lat.step(steps)
+    f_gpu = lat.populations()
+    _, u_gpu = lat.moments()
+    d = lat.reduce()
+    lat.close()
+    assert d.flags == 0 and d.time == steps
+    m = 3 * steps + 2
+    tf, tu = tols(storage, steps)
+    bad = []
+    for lo in [(172, 124, 124), (124, 124, 124), (252, 250, 251), (100, 170, 30)]:
+        co = syn.window(dims, [a - m for a in lo], [out + 2 * m] * 3)
+        f0 = W.init_equilibrium(wb, rho_fn(co))
+        if storage == "f32":
+            f0 = f0.astype(np.float32).astype(np.float64)
+        # the box is periodic on the oracle's side only: its seams lie outside the interior's light cone
+        with np.errstate(over="ignore", invalid="ignore"):
+            ref = W.run(wb, f0, steps)
+            rho_r, u_r = W.moments(wb, ref)
+        inner = tuple(slice(m, m + out) for _ in range(3))
+        idx = np.ix_(*[(np.arange(out) + lo[a]) % dims[a] for a in (2, 1, 0)])
+        got = f_gpu[(slice(None),) + idx]
+        err = rel_max(got, ref[(slice(None),) + inner])
+        dev = np.abs(got - ref[(slice(None),) + inner])
+        at = np.unravel_index(int(np.argmax(dev)), dev.shape)
+        fmt("wb_window", lo=lo, rel_f=f"{err:.3e}", tol=f"{tf:.1e}", worst=at, f=f"{float(ref[(slice(None),) + inner][at]):.6e}",
+            rho=f"{float(rho_r[inner][at[1:]]):.6e}", u=f"{abs_max(u_gpu[(slice(None),) + idx], u_r[(slice(None),) + inner]):.2e}")
+        bad += [(lo, "f", err)] if err > tf else []
+        e_rho = rel_max(got.sum(axis=0), rho_r[inner])
+        bad += [(lo, "rho", e_rho)] if e_rho > tf else []
+        e_u = abs_max(u_gpu[(slice(None),) + idx], u_r[(slice(None),) + inner])
+        bad += [(lo, "u", e_u)] if e_u > tu else []
+    assert not bad, bad
+
