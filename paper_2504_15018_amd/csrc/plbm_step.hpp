@@ -315,10 +315,10 @@ __device__ __forceinline__ void wb_force(const C* s_m, const C* s_0, const C* s_
 // populations, f*_0 = f_0 + sum_{i>0} (f_i - f*_i): the same value in exact
 // arithmetic, but (1 - omega) f_0 + omega f_eq,0 inherits the rounding of the
 // density sum every step, the same way at neighbouring nodes, a mass drift
-// that grows linearly (1e-5 to 1e-4 of a settling droplet's mass per 1000
+// that grows linearly (1e-5 to 2e-5 of a settling droplet's mass per 1000
 // steps); the differences are exact near equilibrium and vanish where the
 // moving populations do not change.  float64 keeps the definition's form (its
-// drift is ~1e-13 per 1000 steps, and it stays on the oracle's rounding path).
+// drift is ~2e-13 in 4000 steps, and it stays on the oracle's rounding path).
 template <class L, class C, int COLL, bool WB = false>
 __device__ __forceinline__ void collide(const C* f, const C* dp, C rho, const C* u, const C* F, C omega,
                                         const C* rate, C* fs, C rho0 = (C)0) {
