@@ -228,7 +228,7 @@ def stream_probe(torch, nodes=256 ** 3, reps=50):
                                         ctypes.c_void_p]
     lib.plbm_probe_stream19_lds.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                             ctypes.c_void_p]
-    lib.plbm_probe_read19.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    lib.plbm_probe_read19.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p]
     lib.plbm_probe_copy4nt.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
     lib.plbm_probe_stream19x.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_void_p]
@@ -261,17 +261,17 @@ def stream_probe(torch, nodes=256 ** 3, reps=50):
             ("pingpong_plain_stores_reversed",
              lambda: lib.plbm_probe_pingpong(a.data_ptr(), b.data_ptr(), nodes, 0, 1, sp)),
             # read-mostly passes (19 values read, one written per node); rates of those bytes
-            ("read19_linear", lambda: lib.plbm_probe_read19(a.data_ptr(), b.data_ptr(), 0, sp)),
-            ("read19_tiles_per_plane", lambda: lib.plbm_probe_read19(a.data_ptr(), b.data_ptr(), 1, sp)),
-            ("read19_tile_columns_2", lambda: lib.plbm_probe_read19(a.data_ptr(), b.data_ptr(), 2, sp)),
-            ("read19_tile_columns_16", lambda: lib.plbm_probe_read19(a.data_ptr(), b.data_ptr(), 3, sp)),
+            ("read19_linear", lambda: lib.plbm_probe_read19(a.data_ptr(), b.data_ptr(), nodes, 0, sp)),
+            ("read19_tiles_per_plane", lambda: lib.plbm_probe_read19(a.data_ptr(), b.data_ptr(), nodes, 1, sp)),
+            ("read19_tile_columns_2", lambda: lib.plbm_probe_read19(a.data_ptr(), b.data_ptr(), nodes, 2, sp)),
+            ("read19_tile_columns_16", lambda: lib.plbm_probe_read19(a.data_ptr(), b.data_ptr(), nodes, 3, sp)),
             # 16-bit populations: half the bytes (the rates below are of those bytes)
             ("half_stream19", lambda: lib.plbm_probe_stream19h(a.data_ptr(), b.data_ptr(), nodes, 1, sp)),
             ("half_stream19_2_per_thread", lambda: lib.plbm_probe_stream19h(a.data_ptr(), b.data_ptr(), nodes, 2, sp)),
             ("half_stream19_4_per_thread", lambda: lib.plbm_probe_stream19h(a.data_ptr(), b.data_ptr(), nodes, 4, sp)),
             ("copy4_nontemporal", lambda: lib.plbm_probe_copy4nt(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp)),
             ("copy4_4_per_thread", lambda: lib.plbm_probe_copy4u(a.data_ptr(), b.data_ptr(), 19 * 4 * nodes, sp))]
-    if nodes != 256 ** 3:  # the read-mostly kernels index a cube of side 256
+    if nodes != 256 ** 3:  # the read-mostly kernels index a cube of side 256 (and refuse other sizes)
         runs = [r for r in runs if not r[0].startswith("read19")]
     for name, fn in runs:
         t = timed(fn)

@@ -293,9 +293,10 @@ int plbm_probe_stream19h(const void* src, void* dst, uint32_t nodes, int vec, vo
 }
 
 // Read-mostly pass over a 256^3 cube (src: 19 * 256^3 floats, dst: 256^3
-// floats); order 0, 1 as k_probe_read19, 2 and 3 its tile columns in 2 and 16
-// chunks.
-int plbm_probe_read19(const void* src, void* dst, int order, void* stream) {
+// floats; nodes must be 256^3); order 0, 1 as k_probe_read19, 2 and 3 its tile
+// columns in 2 and 16 chunks.
+int plbm_probe_read19(const void* src, void* dst, uint32_t nodes, int order, void* stream) {
+  if (nodes != 256u * 256u * 256u) return (int)hipErrorInvalidValue;
   const hipStream_t st = (hipStream_t)stream;
   const float* s = (const float*)src;
   float* d = (float*)dst;
