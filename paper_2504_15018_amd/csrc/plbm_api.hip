@@ -363,13 +363,13 @@ bool graphs_enabled() {
 // Steps of the long replay graph (one graph launch carries many kernels, so
 // the gap the runtime leaves between consecutive graph launches, about 8 us on
 // MI355X, is paid once per that many steps); PLBM_LONG_GRAPH overrides (an
-// even count >= 4; 0: two-step graphs only), read once.
+// even count from 4 to 1024; anything else: two-step graphs only), read once.
 int long_steps() {
   static const int n = [] {
     const char* e = std::getenv("PLBM_LONG_GRAPH");
     if (!e) return 16;
     const int v = std::atoi(e);
-    return (v >= 4 && v % 2 == 0) ? v : 0;
+    return (v >= 4 && v <= 1024 && v % 2 == 0) ? v : 0;  // even: each replay starts at phase 0
   }();
   return n;
 }
