@@ -20,6 +20,8 @@ precision).  Arithmetic is float32 in all four; psi is evaluated in float64.
    10 000 steps, MRT, T/Tc = 0.8): densities at the centre and in the far
    field, the Laplace jump p_EOS(centre) - p_EOS(far field) and the
    spurious-current maximum in every storage against the float64 run.
+4. The 384 x 384 x 128 channel itself, two updates in every 16-bit format:
+   full-height columns against the oracle at the bar of item 1.
 """
 import numpy as np
 import pytest
@@ -190,3 +192,53 @@ def test_droplet_laplace_jump_and_spurious_currents_by_storage(spec):
         bars = DROPLET_BARS[lattice].get(st)
         if bars is not None:
             assert v[4] == 0 and all(e <= b for e, b in zip(err, bars)), (st, err, bars)
+
+
+def test_c4_channel_full_size_every_16bit_format_against_the_oracle():
+    """The precision form's workload at full size: D3Q19 384 x 384 x 128 between plates on z, F_g = 1e-6 x,
+    BGK tau = 1, two updates from a state representable in each 16-bit format, replayed from the step graph as
+    the benchmark does.  Two updates reach populations two nodes away and psi one further (4 nodes), so
+    8 x 8 columns of the full height (wrapped across the x and y faces, mid-lattice, near the far faces) must
+    match the oracle run on 16 x 16 x 128 boxes (periodic in x and y, the plates on z) to the one-step bar of
+    the small-lattice test."""
+    require_gpu()
+    import plbm_synth as syn
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("precision_c4_fullsize")
+    dims, steps, out, seed = (384, 384, 128), 2, 8, 7
+    m = 2 * steps
+    Fg = (1e-6, 0.0, 0.0)
+    op = oracle_params("D3Q19", walls=True, Fg=Fg)
+    rv, rl, _ = pr_coex(0.8)
+    Q = LATTICES["D3Q19"].Q
+
+    def state(co):  # the generator of gpu_cases.random_state, on any (wrapped) coordinates
+        rho = syn.droplet(co, dims, rv, rl, R=min(dims) / 3.0, W=4.0, centre=[n / 2.0 - 0.3 for n in dims])
+        return syn.random_populations(Q, co, dims, seed, rho, 0.3)
+
+    f_in = state(syn.grid(dims))
+    w = LATTICES["D3Q19"].w.reshape((-1, 1, 1, 1))
+    for storage in ["f16r", "bf16r", "f16s", "bf16s"]:
+        lat = Lattice("D3Q19", dims, lib_params(Fg=Fg), storage=storage, walls=True,
+                      rho0_shift=rl if storage.endswith("s") else 0.0)
+        lat.write_populations(f_in)
+        lat.step(steps)
+        f_gpu = lat.populations()
+        d = lat.reduce()
+        lat.close()
+        assert d.flags == 0 and d.time == steps
+        for x0, y0 in [(0, 0), (188, 190), (380, 100)]:
+            co = syn.window(dims, (x0 - m, y0 - m, 0), (out + 2 * m, out + 2 * m, dims[2]))
+            f0 = storage_round("D3Q19", state(co), storage, rl)
+            ref = S.run(op, f0, steps)[:, :, m:m + out, m:m + out]
+            idx = np.ix_(np.arange(dims[2]), (np.arange(out) + y0) % dims[1], (np.arange(out) + x0) % dims[0])
+            got = f_gpu[(slice(None),) + idx]
+            if storage.endswith("s"):
+                dev = np.max(np.abs(ref - w * rl))
+            else:
+                dev = np.max(np.abs(ref - w * ref.sum(axis=0)[None]))
+            tol = steps * (ULP[storage] * dev / np.max(np.abs(ref)) + 2e-6)
+            err = rel_max(got, ref)
+            fmt("precision_c4_window", storage=storage, x0=x0, y0=y0, err=f"{err:.3e}", tol=f"{tol:.3e}")
+            assert err <= tol, (storage, x0, y0, err, tol)
+        del f_gpu
