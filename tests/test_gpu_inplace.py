@@ -10,6 +10,8 @@
   parities, the graph path for n >= 8) and in every storage type, the locally
   shifted ones included.
 * In a continuous batch mixed with A-B lattices: bitwise equal to solo runs.
+* At the benchmark's 256^3, in every storage format: bitwise equal to the A-B
+  pattern after 19 steps.
 """
 import numpy as np
 import pytest
@@ -159,3 +161,30 @@ def test_inplace_in_a_batch_matches_solo_bitwise():
     b.close()
     for lat in solo + mixed:
         lat.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16s", "bf16s", "f16r", "bf16r"])
+def test_inplace_equals_ab_at_the_benchmark_size(storage):
+    """The benchmark's 256^3 MRT droplet, 19 steps (graph replays and a single launch; the in-place lattice ends in
+    its odd-time layout), in the launch configuration `bench.py --pattern aa --storage X` times: populations and
+    moments equal to the A-B pattern's, bitwise, in every storage format (the two patterns tile differently in
+    float64 and the 16-bit formats)."""
+    require_gpu()
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("inplace_fullsize", storage=storage)
+    dims = (256, 256, 256)
+    prm = lib_params()
+    got = {}
+    for pattern in ("ab", "aa"):
+        lat = Lattice("D3Q19", dims, prm, collision="mrt", storage=storage, pattern=pattern)
+        lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=5.0, R=48.0, centre=[128.0] * 3)
+        lat.step(19)
+        rho, u = lat.moments()
+        got[pattern] = (lat.populations(), rho, u, lat.reduce())
+        lat.close()
+    (fa, ra, ua, da), (fb, rb, ub, db) = got["ab"], got["aa"]
+    assert np.array_equal(fa, fb)
+    assert np.array_equal(ra, rb) and np.array_equal(ua, ub)
+    assert da.max_u == db.max_u and da.flags == db.flags == 0
+    assert da.mass == pytest.approx(db.mass, rel=1e-14)
