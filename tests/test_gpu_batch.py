@@ -4,7 +4,9 @@ Each lattice advanced inside a batch, whatever else shares the launches and
 whenever it joins or leaves, must be bitwise identical to the same lattice
 stepped alone (the kernels compute every node with the same arithmetic; the
 batch only changes which workgroup handles which tile).  The per-slot
-diagnostics must equal plbm_reduce of a solo lattice.
+diagnostics must equal plbm_reduce of a solo lattice.  Covered at small,
+ragged sizes with joins and leaves, and at the serving workload's extremes
+(192^3 and 1024^2 beside 64^3 and 64^2).
 """
 import numpy as np
 import pytest
@@ -170,4 +172,42 @@ def test_batch_owns_its_lattices_until_detached():
         assert mixed[k].time == steps
         assert np.array_equal(mixed[k].populations(), solo[k].populations()), specs[k]
     for lat in solo + [mixed[0], mixed[2]]:
+        lat.close()
+
+
+def test_batch_of_the_serving_extremes_matches_solo_bitwise():
+    """The serving workload's largest and smallest lattices in one batch (D3Q19 192^3 and 64^3, D2Q9 1024^2 and
+    64^2; f32, MRT, static droplets as the serving loop initialises them), 21 steps: every lattice bitwise equal
+    to the same lattice stepped alone, and the per-slot diagnostics equal to its solo reduction."""
+    require_gpu()
+    import torch
+    from paper_2504_15018_amd import native as N
+    from paper_2504_15018_amd.lattice import Lattice
+    fmt("batch_serving_extremes")
+    specs = [("D3Q19", (192, 192, 192)), ("D2Q9", (1024, 1024)), ("D3Q19", (64, 64, 64)), ("D2Q9", (64, 64))]
+    prm = lib_params(tr=0.75)
+
+    def make(lattice, dims, stream=None):
+        lat = Lattice(lattice, dims, prm, collision="mrt", storage="f32", stream=stream)
+        lat.init_shape(N.PLBM_SHAPE_DROPLET, prm.rho_l, prm.rho_v, W=5.0, R=0.3 * dims[0],
+                       centre=[n / 2.0 for n in dims])
+        return lat
+
+    stream = torch.cuda.Stream()
+    solo = [make(*s) for s in specs]
+    mixed = [make(*s, stream=stream) for s in specs]
+    b = Batch(4, 65536, stream)
+    slots = [b.attach(lat) for lat in mixed]
+    b.step(21)
+    stream.synchronize()
+    d = b.diag()
+    for lat in solo:
+        lat.step(21)
+    for k, spec in enumerate(specs):
+        assert np.array_equal(mixed[k].populations(), solo[k].populations()), spec
+        ref = solo[k].reduce()
+        assert d[slots[k]].mass == ref.mass and d[slots[k]].max_u == ref.max_u, spec
+        assert d[slots[k]].flags == 0 and d[slots[k]].time == 21
+    b.close()
+    for lat in solo + mixed:
         lat.close()
