@@ -65,17 +65,18 @@ def _window_parity(lat, op, rho_fn, u0, dims, storage, steps, windows, out_size)
     return f_gpu
 
 
-@pytest.mark.parametrize("variant", ["static", "galilean", "static-inplace"])
-def test_c3_droplet_256cubed_f32_mrt_windows(variant):
+@pytest.mark.parametrize("variant", ["static", "galilean", "static-inplace", "static-f64", "galilean-inplace-f64"])
+def test_c3_droplet_256cubed_mrt_windows(variant):
     """D3Q19 256^3, float32 MRT + Guo, PR T/Tc = 0.8, droplet R = 48 (W = 5); Galilean variant u0 = 0.05 x;
-    the in-place pattern over an odd step count (ends in the odd-time layout)."""
+    the in-place pattern over an odd step count (ends in the odd-time layout); the same in float64 storage
+    (`bench.py --storage f64`), at the float64 bar."""
     require_gpu()
     from paper_2504_15018_amd.lattice import Lattice
     fmt("c3_fullsize", variant=variant)
     dims = (256, 256, 256)
     op = oracle_params("D3Q19", collision="mrt")
     rv, rl = op.rho_v, op.rho_l
-    u0 = (0.05, 0.0, 0.0) if variant == "galilean" else (0.0, 0.0, 0.0)
+    u0 = (0.05, 0.0, 0.0) if variant.startswith("galilean") else (0.0, 0.0, 0.0)
 
     def rho_fn(co):
         return syn.droplet(co, dims, rv, rl, R=48.0, W=5.0)
@@ -85,14 +86,15 @@ def test_c3_droplet_256cubed_f32_mrt_windows(variant):
     del co
     u_full = np.zeros((3,) + rho_full.shape)
     u_full[0] = u0[0]
-    inplace = variant.endswith("inplace")
-    lat = Lattice("D3Q19", dims, lib_params(), collision="mrt", storage="f32", pattern="aa" if inplace else "ab")
+    inplace = "inplace" in variant
+    storage = "f64" if variant.endswith("f64") else "f32"
+    lat = Lattice("D3Q19", dims, lib_params(), collision="mrt", storage=storage, pattern="aa" if inplace else "ab")
     lat.init_fields(rho_full, u_full)
     del u_full
     steps = 13 if inplace else 12
     lat.step(steps)
     windows = [(172, 124, 124), (124, 124, 124), (252, 250, 251), (100, 170, 30)]
-    _window_parity(lat, op, rho_fn, u0, dims, "f32", steps, windows, 8)
+    _window_parity(lat, op, rho_fn, u0, dims, storage, steps, windows, 8)
     lat.close()
 
 
