@@ -231,18 +231,24 @@ def stream_probe(torch, nodes=256 ** 3, reps=50):
     lib.plbm_probe_read19.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p]
     lib.plbm_probe_copy4nt.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
     lib.plbm_probe_stream19x.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
-                                         ctypes.c_void_p]
+                                         ctypes.c_uint32, ctypes.c_void_p]
     moved = 2 * 19 * 4 * nodes
     out = {"nodes": nodes}
     runs = [("stream19_blocked", lambda: lib.plbm_probe_stream19(a.data_ptr(), b.data_ptr(), nodes, sp)),
             ("stream19_blocked_2_per_thread", lambda: lib.plbm_probe_stream19v(a.data_ptr(), b.data_ptr(), nodes, 2, sp)),
             ("stream19_blocked_4_per_thread", lambda: lib.plbm_probe_stream19v(a.data_ptr(), b.data_ptr(), nodes, 4, sp)),
-            ("stream19_blocks_of_64", lambda: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, 64, 1, sp)),
+            ("stream19_blocks_of_64", lambda: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, 64, 1, 0, sp)),
             ("stream19_blocks_of_64_2_per_thread",
-             lambda: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, 64, 2, sp)),
-            ("stream19_blocks_of_128", lambda: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, 128, 1, sp)),
+             lambda: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, 64, 2, 0, sp)),
+            ("stream19_blocks_of_128", lambda: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, 128, 1, 0, sp)),
             ("stream19_blocks_of_128_2_per_thread",
-             lambda: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, 128, 2, sp)),
+             lambda: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, 128, 2, 0, sp)),
+            ("stream19_blocks_of_128_4_per_thread",
+             lambda: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, 128, 4, 0, sp)),
+            # the same with three workgroups per CU (unused LDS), the cap that suits the one-node stream
+            *[(f"stream19_blocks_of_{xb}_{v}_per_thread_lds_53k",
+               (lambda xb=xb, v=v: lib.plbm_probe_stream19x(a.data_ptr(), b.data_ptr(), nodes, xb, v, 53 * 1024, sp)))
+              for xb, v in ((64, 2), (128, 2), (128, 4))],
             ("stream19_plain_stores", lambda: lib.plbm_probe_stream19s(a.data_ptr(), b.data_ptr(), nodes, 0, 0, sp)),
             ("stream19_plain_stores_interleaved",
              lambda: lib.plbm_probe_stream19s(a.data_ptr(), b.data_ptr(), nodes, 0, 1, sp)),

@@ -11,7 +11,9 @@
 // k_probe_stream19v<V>: the same bytes and layout with V = 2 or 4 consecutive
 // nodes per thread (8- or 16-byte accesses per direction).
 // k_probe_stream19x<XB, V>: the same bytes in blocks of XB = 32, 64 or 128
-// nodes (128, 256 or 512 bytes per direction), V = 1 or 2 nodes per thread.
+// nodes (128, 256 or 512 bytes per direction), V = 1, 2 or 4 nodes per thread
+// (4: XB = 128 only, a wave's access one contiguous 1 KiB per direction),
+// optionally with unused dynamic LDS capping the workgroups per CU.
 // k_probe_stream19s<NT, ORDER>: blocks of 32 nodes, one node per thread, with
 // plain (NT = 0) or non-temporal stores, all loads before the stores
 // (ORDER = 0) or each direction stored right after its load (ORDER = 1).
@@ -245,20 +247,22 @@ int plbm_probe_stream19v(const void* src, void* dst, uint32_t nodes, int vec, vo
 
 // Blocks of xb = 32, 64 or 128 nodes, vec = 1 or 2 nodes per thread; nodes a
 // multiple of xb; src and dst hold 19 * nodes floats each.
-int plbm_probe_stream19x(const void* src, void* dst, uint32_t nodes, int xb, int vec, void* stream) {
+int plbm_probe_stream19x(const void* src, void* dst, uint32_t nodes, int xb, int vec, uint32_t lds, void* stream) {
   if (nodes == 0) return 0;
-  if ((xb != 32 && xb != 64 && xb != 128) || (vec != 1 && vec != 2) || nodes % (uint32_t)xb)
+  if ((xb != 32 && xb != 64 && xb != 128) || (vec != 1 && vec != 2 && vec != 4) || (vec == 4 && xb != 128) ||
+      nodes % (uint32_t)xb || lds > 65536u)
     return (int)hipErrorInvalidValue;
   const dim3 g((nodes / (uint32_t)vec + 255u) / 256u), b(256);
   const hipStream_t st = (hipStream_t)stream;
   const float* s = (const float*)src;
   float* d = (float*)dst;
-  if (xb == 32 && vec == 1) hipLaunchKernelGGL((k_probe_stream19x<32, 1>), g, b, 0, st, s, d, nodes);
-  if (xb == 32 && vec == 2) hipLaunchKernelGGL((k_probe_stream19x<32, 2>), g, b, 0, st, s, d, nodes);
-  if (xb == 64 && vec == 1) hipLaunchKernelGGL((k_probe_stream19x<64, 1>), g, b, 0, st, s, d, nodes);
-  if (xb == 64 && vec == 2) hipLaunchKernelGGL((k_probe_stream19x<64, 2>), g, b, 0, st, s, d, nodes);
-  if (xb == 128 && vec == 1) hipLaunchKernelGGL((k_probe_stream19x<128, 1>), g, b, 0, st, s, d, nodes);
-  if (xb == 128 && vec == 2) hipLaunchKernelGGL((k_probe_stream19x<128, 2>), g, b, 0, st, s, d, nodes);
+  if (xb == 32 && vec == 1) hipLaunchKernelGGL((k_probe_stream19x<32, 1>), g, b, lds, st, s, d, nodes);
+  if (xb == 32 && vec == 2) hipLaunchKernelGGL((k_probe_stream19x<32, 2>), g, b, lds, st, s, d, nodes);
+  if (xb == 64 && vec == 1) hipLaunchKernelGGL((k_probe_stream19x<64, 1>), g, b, lds, st, s, d, nodes);
+  if (xb == 64 && vec == 2) hipLaunchKernelGGL((k_probe_stream19x<64, 2>), g, b, lds, st, s, d, nodes);
+  if (xb == 128 && vec == 1) hipLaunchKernelGGL((k_probe_stream19x<128, 1>), g, b, lds, st, s, d, nodes);
+  if (xb == 128 && vec == 2) hipLaunchKernelGGL((k_probe_stream19x<128, 2>), g, b, lds, st, s, d, nodes);
+  if (xb == 128 && vec == 4) hipLaunchKernelGGL((k_probe_stream19x<128, 4>), g, b, lds, st, s, d, nodes);
   return (int)hipGetLastError();
 }
 
